@@ -1,0 +1,241 @@
+"""Workload recipes: plasma loading and the laser initial condition.
+
+Units are normalized laser units: time in 1/omega0, length in c/omega0 (one
+wavelength is 2*pi), momentum u = gamma*beta of each species, fields in
+m_e*c*omega0/e and densities in the critical density n_c.  The paper's runs
+(section 2: a circularly polarized pulse into a near-critical gas, all
+protons spin-aligned along y, two macro-particles per species per cell) are
+not reproducible here, so these seeded synthetic plasmas of the same
+structure stand in for them:
+
+* ``c1``: 2D 256x128 cells of 0.05 wavelengths, uniform e/p plasma at
+  0.01 n_c, 4 per cell per species, 1 keV, linearly polarized a0=3 pulse with
+  a 4-wavelength waist and 10-wavelength duration, spins +y, FP64.
+* ``c2``: 2D 4096x1024, 8 per cell per species, density ramp 0 -> 0.02 n_c over
+  50 wavelengths then flat, a0=10, waist 8, duration 15, spins +y.
+* ``c3``: 3D 512x256x256 cells of 0.1 wavelengths, 2 per cell per species,
+  0.005 n_c with a 1 % per-cell density noise, circular a0=20, waist 6,
+  duration 10, spins +x.
+
+Every random draw comes from a numpy PCG64 stream seeded by the recipe.
+"""
+
+import math
+
+import numpy as np
+
+LAMBDA = 2.0 * math.pi          # one laser wavelength in c/omega0
+ME_C2_MEV = 0.51099895          # electron rest energy
+ME_C2_KEV = ME_C2_MEV * 1e3
+MP_OVER_ME = 1836.15267343      # proton/electron mass ratio
+A_E = 0.00116                   # electron anomaly used by the workloads
+A_P = 1.793                     # proton anomaly used by the workloads
+
+PARTICLE_COLUMNS = ("x", "y", "z", "ux", "uy", "uz", "sx", "sy", "sz", "w")
+
+
+def electron():
+    return {"name": "e", "Z": -1.0, "mu": 1.0, "a": A_E}
+
+
+def proton():
+    return {"name": "p", "Z": 1.0, "mu": MP_OVER_ME, "a": A_P}
+
+
+def courant_dt(d, ndim, courant=0.95):
+    """Time step as a fraction of the Yee stability limit (c = 1)."""
+    return courant / math.sqrt(sum(1.0 / (d[i] * d[i]) for i in range(ndim)))
+
+
+def grid_shape(spec):
+    """Array shape of one field component, (nz, ny, nx); nz = 1 in 2D."""
+    nx, ny, nz = spec["n"]
+    return (nz, ny, nx)
+
+
+def _base(name, ndim, n, d_lambda, steps, seed, precision, tile):
+    d = tuple(float(v) * LAMBDA for v in d_lambda)
+    n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+    d = d + (d[0],) * (3 - len(d))
+    return {
+        "name": name, "ndim": ndim, "n": n, "d": d,
+        "dt": courant_dt(d, ndim), "steps": steps, "seed": seed,
+        "precision": precision, "tile": tile,
+        "species": [electron(), proton()],
+    }
+
+
+def _c1(**kw):
+    s = _base("c1", 2, (256, 128), (0.05, 0.05), 200, 1, "fp64", (16, 16, 1))
+    s["plasma"] = {"ppc": 4, "profile": "uniform", "n0": 0.01, "ramp_len": 0.0,
+                   "noise": 0.0, "T_keV": 1.0, "s0": (0.0, 1.0, 0.0)}
+    s["laser"] = {"a0": 3.0, "waist": 4 * LAMBDA, "duration": 10 * LAMBDA,
+                  "x_center": 0.5 * 256 * s["d"][0], "pol": "lp"}
+    s.update(kw)
+    return s
+
+
+def _c2(**kw):
+    s = _base("c2", 2, (4096, 1024), (0.05, 0.05), 1000, 2, "fp32", (16, 16, 1))
+    s["plasma"] = {"ppc": 8, "profile": "ramp", "n0": 0.02, "ramp_len": 50 * LAMBDA,
+                   "noise": 0.0, "T_keV": 1.0, "s0": (0.0, 1.0, 0.0)}
+    s["laser"] = {"a0": 10.0, "waist": 8 * LAMBDA, "duration": 15 * LAMBDA,
+                  "x_center": 15 * LAMBDA, "pol": "lp"}
+    s.update(kw)
+    return s
+
+
+def _c3(**kw):
+    s = _base("c3", 3, (512, 256, 256), (0.1, 0.1, 0.1), 500, 3, "fp32", (8, 8, 8))
+    s["plasma"] = {"ppc": 2, "profile": "uniform", "n0": 0.005, "ramp_len": 0.0,
+                   "noise": 0.01, "T_keV": 1.0, "s0": (1.0, 0.0, 0.0)}
+    s["laser"] = {"a0": 20.0, "waist": 6 * LAMBDA, "duration": 10 * LAMBDA,
+                  "x_center": 10 * LAMBDA, "pol": "cp"}
+    s.update(kw)
+    return s
+
+
+def _small2d(**kw):
+    """A c1-like plasma on a 72x40 grid: several 16x16 tiles and ragged last tiles."""
+    s = _base("small2d", 2, (72, 40), (0.05, 0.05), 40, 11, "fp64", (16, 16, 1))
+    s["plasma"] = {"ppc": 3, "profile": "ramp", "n0": 0.05, "ramp_len": 2 * LAMBDA,
+                   "noise": 0.02, "T_keV": 5.0, "s0": (0.0, 1.0, 0.0)}
+    s["laser"] = {"a0": 3.0, "waist": 1.0 * LAMBDA, "duration": 1.5 * LAMBDA,
+                  "x_center": 1.8 * LAMBDA, "pol": "lp"}
+    s.update(kw)
+    return s
+
+
+def _small3d(**kw):
+    s = _base("small3d", 3, (20, 12, 10), (0.1, 0.1, 0.1), 20, 12, "fp64", (8, 8, 8))
+    s["plasma"] = {"ppc": 2, "profile": "uniform", "n0": 0.05, "ramp_len": 0.0,
+                   "noise": 0.02, "T_keV": 5.0, "s0": (1.0, 0.0, 0.0)}
+    s["laser"] = {"a0": 3.0, "waist": 0.4 * LAMBDA, "duration": 0.8 * LAMBDA,
+                  "x_center": 1.0 * LAMBDA, "pol": "cp"}
+    s.update(kw)
+    return s
+
+
+PRESETS = {"c1": _c1, "c2": _c2, "c3": _c3, "small2d": _small2d, "small3d": _small3d}
+
+
+def preset(name, **overrides):
+    """A workload recipe by name; keyword arguments replace top-level keys."""
+    return PRESETS[name](**overrides)
+
+
+def _density_weight(spec, x_first):
+    p = spec["plasma"]
+    ppc = p["ppc"]
+    if p["profile"] == "uniform":
+        return np.full(x_first.shape, p["n0"] / ppc)
+    if p["profile"] == "ramp":
+        ramp = np.minimum(x_first / p["ramp_len"], 1.0) if p["ramp_len"] > 0 else 1.0
+        return p["n0"] * ramp / ppc
+    raise ValueError("unknown density profile %r" % p["profile"])
+
+
+def make_particles(spec, seed=None):
+    """Plasma particles, one float64 array of shape (N, 10) per species.
+
+    Columns are x, y, z, ux, uy, uz, sx, sy, sz, w.  Every cell holds ``ppc``
+    particles of each species at uniform random positions inside the cell;
+    electrons and protons share positions and weights, so the initial charge
+    density is exactly zero.  Momenta are drawn from a non-relativistic
+    Maxwellian of temperature T_keV; spins all equal s0; the weight is the
+    local density over ppc, times a per-cell noise factor when requested.
+    In 2D the z column is 0.
+    """
+    rng = np.random.Generator(np.random.PCG64(spec["seed"] if seed is None else seed))
+    ndim = spec["ndim"]
+    nx, ny, nz = spec["n"]
+    dx, dy, dz = spec["d"]
+    p = spec["plasma"]
+    ppc = p["ppc"]
+    ncell = nx * ny * (nz if ndim == 3 else 1)
+    npart = ncell * ppc
+    cell = np.repeat(np.arange(ncell, dtype=np.int64), ppc)
+    pos = np.empty((npart, 3))
+    pos[:, 0] = (cell % nx + rng.random(npart)) * dx
+    pos[:, 1] = ((cell // nx) % ny + rng.random(npart)) * dy
+    if ndim == 3:
+        pos[:, 2] = (cell // (nx * ny) + rng.random(npart)) * dz
+    else:
+        pos[:, 2] = 0.0
+    w = _density_weight(spec, pos[:, 0])
+    if p["noise"] > 0:
+        factor = 1.0 + p["noise"] * rng.standard_normal(ncell)
+        w = w * factor[cell]
+    del cell
+    out = []
+    for sp in spec["species"]:
+        arr = np.empty((npart, 10))
+        arr[:, 0:3] = pos
+        sigma = math.sqrt(p["T_keV"] / (sp["mu"] * ME_C2_KEV))
+        arr[:, 3:6] = sigma * rng.standard_normal((npart, 3))
+        arr[:, 6:9] = np.asarray(p["s0"], dtype=np.float64)
+        arr[:, 9] = w
+        out.append(arr)
+    return out
+
+
+def _envelope(spec, x, y, z):
+    las = spec["laser"]
+    ndim = spec["ndim"]
+    nx, ny, nz = spec["n"]
+    dx, dy, dz = spec["d"]
+    xi = x - las["x_center"]
+    r2 = (y - 0.5 * ny * dy) ** 2
+    if ndim == 3:
+        r2 = r2 + (z - 0.5 * nz * dz) ** 2
+    length = las["duration"]
+    g = np.exp(-2.0 * math.log(2.0) * xi * xi / (length * length))
+    f = np.exp(-r2 / (las["waist"] ** 2))
+    return las["a0"] * g * f, xi
+
+
+def make_laser_fields(spec):
+    """Initial E and B of the pulse, shape (6, nz, ny, nx): Ex Ey Ez Bx By Bz.
+
+    The pulse travels along +x, focused, without wavefront curvature or a
+    longitudinal field.  Its transverse field is a0*g*f*cos(x - xc) along y
+    (plus a0*g*f*sin(x - xc) along z when circular), with g a Gaussian of
+    intensity FWHM equal to the duration and f = exp(-r^2/waist^2); B is x-hat
+    cross E.  Each component is evaluated at its own staggered Yee position.
+    """
+    ndim = spec["ndim"]
+    nx, ny, nz = spec["n"]
+    dx, dy, dz = spec["d"]
+    shape = grid_shape(spec)
+    F = np.zeros((6,) + shape)
+    las = spec.get("laser")
+    if not las or las["a0"] == 0.0:
+        return F
+    k = np.arange(shape[0], dtype=np.float64)[:, None, None]
+    j = np.arange(ny, dtype=np.float64)[None, :, None]
+    i = np.arange(nx, dtype=np.float64)[None, None, :]
+    def at(sx, sy, sz):
+        return (i + sx) * dx, (j + sy) * dy, (k + (sz if ndim == 3 else 0.0)) * dz
+
+    cp = las["pol"] == "cp"
+    # E_y at (i, j+1/2, k); B_z at (i+1/2, j+1/2, k)
+    amp, xi = _envelope(spec, *at(0.0, 0.5, 0.0))
+    F[1] = amp * np.cos(xi)
+    amp, xi = _envelope(spec, *at(0.5, 0.5, 0.0))
+    F[5] = amp * np.cos(xi)
+    if cp:
+        # E_z at (i, j, k+1/2); B_y at (i+1/2, j, k+1/2)
+        amp, xi = _envelope(spec, *at(0.0, 0.0, 0.5))
+        F[2] = amp * np.sin(xi)
+        amp, xi = _envelope(spec, *at(0.5, 0.0, 0.5))
+        F[4] = -amp * np.sin(xi)
+    return F
+
+
+def make_state(spec, with_particles=True):
+    """Everything the simulation starts from: particles per species and fields."""
+    return {
+        "particles": make_particles(spec) if with_particles else [
+            np.zeros((0, 10)) for _ in spec["species"]],
+        "fields": make_laser_fields(spec),
+    }
