@@ -1,0 +1,209 @@
+"""Throughput of the spin-resolved PIC step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+                    [--precision fp32|fp64] [--no-cpu-baseline]
+
+A step is one full pass of the hot path over every particle: gather, Boris
+push, Thomas-BMT spin rotation, move and Esirkepov deposit (one fused kernel
+per tile), the rebinning of tile leavers, and the Yee field update.  Inputs
+are the seeded synthetic plasma of the workload (default c2: 2D3V,
+4096x1024 cells, electrons and protons at 8 per cell each, 67,108,864
+particles), resident in HBM before timing starts.  Prints one JSON line.
+"""
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-resolved particle-pushes/sec (gather+push+spin+deposit), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD_TEXT = {
+    "c1": "2D3V PIC, 256x128 cells of 0.05 lambda, e+p at 4 per cell each (262,144 particles), "
+          "uniform 0.01 n_c, 1 keV, LP a0=3 pulse, spins +y",
+    "c2": "2D3V PIC, 4096x1024 cells of 0.05 lambda, e+p at 8 per cell each (67,108,864 particles), "
+          "density ramp 0->0.02 n_c over 50 lambda, 1 keV, LP a0=10 waist 8 lambda duration 15 lambda/c, "
+          "spins +y",
+    "c3": "3D3V PIC, 512x256x256 cells of 0.1 lambda, e+p at 2 per cell each (134,217,728 particles), "
+          "0.005 n_c with 1% noise, 1 keV, CP a0=20 waist 6 lambda, spins +x",
+}
+
+
+def algorithmic_bytes(ndim, precision, npart, ncells):
+    """HBM bytes one push+deposit launch must move: every particle's cell,
+    offsets, momentum and spin read and written, its weight read; E and B read
+    and J written once per cell (the grid is FP64 in both precisions)."""
+    r = 8 if precision == "fp64" else 4
+    read = 4 + ndim * r + 3 * r + 3 * r + r
+    write = 4 + ndim * r + 3 * r + 3 * r
+    grid = 6 * 8 + 3 * 8
+    return (read + write) * npart + grid * ncells, read + write, grid
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2002_02211_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, launches_bytes):
+    """HBM traffic of the push kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "push_deposit_%s_%s_traffic.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, state, sample_per_species):
+    """The FP64 NumPy oracle, single-threaded, pushing a bounded sample of the
+    same workload's particles through gather+push+spin+deposit once."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ.setdefault(var, "1")
+    import numpy as np
+    import oracle
+    sub = {"particles": [p[:sample_per_species] for p in state["particles"]],
+           "fields": state["fields"]}
+    sim = oracle.Sim(spec, sub)
+    n = sum(p.shape[0] for p in sub["particles"])
+    t0 = time.perf_counter()
+    for k in range(len(spec["species"])):
+        m = sim.xi[k].shape[0]
+        for lo in range(0, m, sim.CHUNK):
+            sim.push_species(k, lo, min(m, lo + sim.CHUNK))
+    dt = time.perf_counter() - t0
+    del sim
+    return {"value": n / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
+            "sample": "%d particles (%d per species, first rows of the same seeded %s state), "
+                      "one gather+push+spin+deposit pass, FP64 NumPy, %.1f s"
+                      % (n, sample_per_species, spec["name"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--precision", default=None, choices=("fp32", "fp64"))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+                    help="particles per species in the CPU-baseline sample")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(domain decomposition over several GPUs is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2002_02211_amd import spinpic as S
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    S.load_library()
+
+    spec = synth.preset(args.workload)
+    precision = args.precision or spec["precision"]
+    t0 = time.time()
+    state = synth.make_state(spec)
+    npart = sum(p.shape[0] for p in state["particles"])
+    print("[bench] %s: %d particles generated in %.1f s" % (args.workload, npart, time.time() - t0),
+          file=sys.stderr, flush=True)
+
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    t0 = time.time()
+    cfg = S.config_from_spec(spec, precision=precision)
+    sim = S.Simulation(cfg, state["particles"], state["fields"])
+    torch.cuda.synchronize()
+    print("[bench] init (sort + upload) %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = sim.timing_read()
+    sim.timing(False)
+    stats = sim.stats()
+    P, N = sim.polarization()
+    print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s N=%d"
+          % (args.steps, elapsed, json.dumps(timers), stats, P, N), file=sys.stderr, flush=True)
+
+    ncells = int(spec["n"][0]) * int(spec["n"][1]) * (int(spec["n"][2]) if spec["ndim"] == 3 else 1)
+    launch_bytes, per_particle, per_cell = algorithmic_bytes(spec["ndim"], precision, npart, ncells)
+    push_ms, push_n = timers["push_deposit"]
+    avg_push_s = push_ms / 1e3 / max(push_n, 1)
+    achieved = launch_bytes / avg_push_s / 1e9
+    traffic = measured_traffic(args.workload, precision, launch_bytes)
+
+    result = {
+        "metric": METRIC,
+        "value": npart * args.steps / elapsed,
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOAD_TEXT[args.workload]),
+                   "particles": npart, "cells": ncells,
+                   "precision": "FP32 particles and push; FP64 fields, currents, reductions"
+                                if precision == "fp32" else "FP64",
+                   "tile": list(cfg.tile)[: spec["ndim"]]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_push_tiles (gather+Boris+T-BMT+move+Esirkepov deposit)",
+                     "bytes_per_launch": launch_bytes,
+                     "bytes_per_particle": per_particle, "bytes_per_cell": per_cell,
+                     "avg_launch_ms": avg_push_s * 1e3,
+                     "push_pushes_per_s": npart / avg_push_s},
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
+    }
+    sim.close()
+    del sim
+    torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, min(p.shape[0] for p in state["particles"]))
+        result["cpu_baseline"] = cpu_baseline(spec, state, sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

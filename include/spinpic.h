@@ -1,0 +1,181 @@
+/*
+ * spinpic.h - C ABI of the spin-resolved particle-in-cell step for MI355X.
+ *
+ * One time step advances every macro-particle and the fields by dt:
+ *   gather E, B at the particle from the staggered Yee grid (first order),
+ *   relativistic Boris push of u = gamma*beta,
+ *   Thomas-BMT spin precession ds/dt = -Omega x s with Omega of section 2
+ *     Eq. 2 and the coefficients of Eq. 3 (a = the species' anomaly),
+ *   position update, charge-conserving (Esirkepov) current deposition,
+ *   Yee FDTD update of E and B.
+ * The polarization of section 2 Eq. 4, P = (1/N) sum s_i over an ensemble
+ * (a species within a kinetic-energy window), is reduced in FP64.
+ *
+ * Units: time 1/omega0, length c/omega0, u = p/(m c) of the species, fields
+ * m_e c omega0 / e, densities (and particle weights) in n_c, J in e n_c c.
+ * A species has charge Z (units of e), mass mu (units of m_e) and anomaly a.
+ *
+ * Conventions for every call:
+ *   - Return value: PIC_OK (0) or a negative PIC_E* code; nothing throws or
+ *     aborts.  pic_last_error() gives a human-readable reason.
+ *   - Host pointers belong to the caller and are only read/written during
+ *     the call.  Device memory belongs to the context; it comes from the
+ *     caller's allocator when one is given, else from hipMalloc.
+ *   - All GPU work is enqueued on the HIP stream given to pic_init.
+ *     pic_step only enqueues (it does not wait for the GPU); every call that
+ *     returns data to the host waits for the stream first.
+ *   - A context is not thread-safe: one host thread at a time per context.
+ */
+#ifndef SPINPIC_H
+#define SPINPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,      /* bad argument or configuration */
+    PIC_ECFL = -2,        /* dt violates the Yee stability (Courant) limit */
+    PIC_EHIP = -3,        /* a HIP runtime call failed */
+    PIC_ECAPACITY = -4,   /* particle storage exhausted */
+    PIC_ENONFINITE = -5,  /* a NaN or Inf was found in the state */
+    PIC_ESTATE = -6,      /* call on a context that is NULL or unusable */
+    PIC_ENOMEM = -7       /* device allocation failed */
+};
+
+enum { PIC_FP64 = 0, PIC_FP32_MIXED = 1 };
+
+/* pic_config.deposit_acc */
+enum { PIC_ACC_DEFAULT = 0, PIC_ACC_FP32 = 1, PIC_ACC_FP64 = 2 };
+
+/* pic_config.flags */
+enum {
+    PIC_FLAG_TEST_PARTICLE = 1  /* fields frozen, no current deposit */
+};
+
+/* pic_fields mask bits; components are returned in this order */
+enum {
+    PIC_EX = 1u << 0, PIC_EY = 1u << 1, PIC_EZ = 1u << 2,
+    PIC_BX = 1u << 3, PIC_BY = 1u << 4, PIC_BZ = 1u << 5,
+    PIC_JX = 1u << 6, PIC_JY = 1u << 7, PIC_JZ = 1u << 8,
+    PIC_RHO = 1u << 9
+};
+
+#define PIC_MAX_SPECIES 4
+#define PIC_PARTICLE_IN_COLS 10   /* x y z ux uy uz sx sy sz w */
+#define PIC_PARTICLE_OUT_COLS 11  /* id x y z ux uy uz sx sy sz w */
+
+typedef struct {
+    double Z;   /* charge in units of e (electron: -1) */
+    double mu;  /* mass in units of m_e (proton: 1836.15267343) */
+    double a;   /* gyromagnetic anomaly of section 2 Eq. 3 */
+} pic_species;
+
+typedef struct {
+    int32_t ndim;        /* 2 (x, y; d/dz = 0, three velocity components) or 3 */
+    int32_t n[3];        /* cells per axis; n[2] is ignored in 2D.
+                            2D: n[0], n[1] <= 65535; 3D: n[0], n[1] <= 2047, n[2] <= 1023 */
+    double d[3];         /* cell size per axis (c/omega0) */
+    double dt;           /* time step (1/omega0); dt^2 * sum 1/d^2 must be < 1 */
+    int32_t precision;   /* PIC_FP64, or PIC_FP32_MIXED: particles stored and pushed
+                            in FP32; E, B, J and the field update stay FP64, and so
+                            do all reductions */
+    int32_t nspecies;    /* 1 .. PIC_MAX_SPECIES */
+    pic_species sp[PIC_MAX_SPECIES];
+    int32_t tile[3];     /* tile edge in cells per axis; 0 selects the default
+                            (16x16 in 2D, 8x8x8 in 3D FP32, 6x6x6 in 3D FP64) */
+    double slack;        /* spare capacity per tile segment as a fraction of its
+                            initial population (>= 0; 0 selects 0.25) */
+    int32_t flags;       /* PIC_FLAG_* */
+    int32_t deposit_acc; /* PIC_FP32_MIXED only: precision of the per-tile
+                            shared-memory current sums that precede the one FP64
+                            global add per node (PIC_ACC_*; default FP64) */
+} pic_config;
+
+/* Initial state, all host memory in float64, copied during pic_init. */
+typedef struct {
+    int64_t count[PIC_MAX_SPECIES];           /* particles per species */
+    const double* particles[PIC_MAX_SPECIES]; /* count[s] rows of PIC_PARTICLE_IN_COLS:
+                                                 x y z (c/omega0; z ignored in 2D),
+                                                 ux uy uz, sx sy sz (|s| = 1), w */
+    const double* fields;  /* 6 components Ex Ey Ez Bx By Bz, each [nz][ny][nx] with
+                              x fastest (nz = 1 in 2D), at their Yee positions;
+                              NULL starts from zero fields */
+} pic_state;
+
+/* Optional device allocator; alloc returns NULL on failure. */
+typedef struct {
+    void* (*alloc)(void* user, size_t bytes);
+    void (*free)(void* user, void* ptr);
+    void* user;
+} pic_allocator;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Validate cfg, copy the initial state to the device sorted by tile, and
+ * return a new context in *out.  Errors: PIC_EINVAL (bad sizes, species,
+ * tile, precision, non-unit spin, non-finite input), PIC_ECFL, PIC_ENOMEM,
+ * PIC_EHIP.  alloc may be NULL; hip_stream may be NULL (the null stream). */
+int pic_init(const pic_config* cfg, const pic_state* init, const pic_allocator* alloc,
+             void* hip_stream, pic_ctx** out);
+
+/* Enqueue nsteps >= 0 full time steps.  Returns PIC_ESTATE on a NULL or
+ * failed context, PIC_EHIP when a launch fails, PIC_ECAPACITY when particle
+ * storage is exhausted. */
+int pic_step(pic_ctx* ctx, int32_t nsteps);
+
+/* Section 2 Eq. 4: mean spin of the particles of one species (species = -1:
+ * all species) whose kinetic energy mu*(gamma-1)*0.51099895 MeV lies in
+ * [ekin_min_mev, ekin_max_mev).  FP64.  Waits for the stream.  With no
+ * particle selected, P_out is 0 and *N_out is 0. */
+int pic_polarization(pic_ctx* ctx, int32_t species, double ekin_min_mev,
+                     double ekin_max_mev, double P_out[3], int64_t* N_out);
+
+/* Copy the masked components (PIC_EX ... PIC_RHO, in bit order) to host_out
+ * as float64, each [nz][ny][nx] with x fastest.  J is the current of the last
+ * step.  cap_doubles must hold popcount(mask)*cells values.  Waits. */
+int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles);
+
+/* Copy the particles of one species, sorted by id (the row index in the
+ * initial state), as rows of PIC_PARTICLE_OUT_COLS float64 values.  cap_doubles
+ * must hold count*11 values; *n_out receives the count.  Waits. */
+int pic_particles(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles,
+                  int64_t* n_out);
+
+/* Diagnostics in FP64: out[0 .. nspecies-1] kinetic energy per species
+ * (sum mu (gamma-1) w V), out[nspecies] field energy (sum (E^2+B^2)/2 V),
+ * out[nspecies+1] max over nodes of |(div E - rho) - (div E - rho) at init|;
+ * V is the cell volume.  cap must be >= nspecies + 2.  Waits. */
+int pic_energy(pic_ctx* ctx, double* out, int32_t cap);
+
+/* Counters since init: out[0] steps, out[1] particles that changed tile,
+ * out[2] particles currently in the overflow store, out[3] repacks done,
+ * out[4] total particles.  cap >= 5.  Waits. */
+int pic_stats(pic_ctx* ctx, int64_t* out, int32_t cap);
+
+/* Per-kernel GPU timing with HIP events on the context's stream.
+ * pic_timing(ctx, 1) starts (and resets) recording, 0 stops it.
+ * pic_timing_read fills ms_out[k] (total milliseconds) and launches_out[k]
+ * for k = 0 push+deposit (including the compaction of the slots tile
+ * leavers vacate), 1 overflow push, 2 insertion of tile leavers, 3 field
+ * update (all three Yee kernels of a step); cap >= 4.  Waits. */
+int pic_timing(pic_ctx* ctx, int32_t enable);
+int pic_timing_read(pic_ctx* ctx, double* ms_out, int64_t* launches_out, int32_t cap);
+
+/* Reason for the last failure on ctx, or of the last failed pic_init on this
+ * thread when ctx is NULL.  Owned by the library; valid until the next call. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* Release every device buffer of ctx (through the allocator it was created
+ * with) after waiting for its stream.  NULL is ignored. */
+void pic_free(pic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPINPIC_H */

@@ -352,10 +352,15 @@ class Sim:
 
     CHUNK = 1 << 20
 
-    def __init__(self, spec, state, test_particle=False):
+    def __init__(self, spec, state, test_particle=False, store_fp32=False):
         self.grid = Grid(spec["ndim"], spec["n"], spec["d"], spec["dt"])
         g = self.grid
         self.test_particle = bool(test_particle)
+        # store_fp32: after every step, round each particle's in-cell offsets,
+        # momentum and spin to float32 (weights once at start), i.e. the exact
+        # method with float32 particle storage.  It bounds the error that any
+        # float32 particle store must incur; the default is plain float64.
+        self.store_fp32 = bool(store_fp32)
         self.species = [(float(sp["Z"]), float(sp["mu"]), float(sp["a"]))
                         for sp in spec["species"]]
         self.xi, self.u, self.s, self.w = [], [], [], []
@@ -368,6 +373,10 @@ class Sim:
             self.u.append(arr[:, 3:6].copy())
             self.s.append(arr[:, 6:9].copy())
             self.w.append(arr[:, 9].copy())
+        if self.store_fp32:
+            for k in range(len(self.xi)):
+                self._round_fp32(k, 0, self.xi[k].shape[0])
+                self.w[k] = self.w[k].astype(np.float32).astype(np.float64)
         F = np.asarray(state["fields"], dtype=np.float64).reshape((6,) + g.shape)
         self.E = F[0:3].copy()
         self.B = F[3:6].copy()
@@ -381,6 +390,21 @@ class Sim:
         for sp, xi, w in zip(self.species, self.xi, self.w):
             rho += charge_density(xi, sp[0] * w, g)
         return rho
+
+    def _round_fp32(self, k, lo, hi):
+        """Round the stored state of particles lo:hi of species k to float32."""
+        def f32(a):
+            return a.astype(np.float32).astype(np.float64)
+        xi = self.xi[k][lo:hi]
+        for a in range(self.grid.ndim):
+            fl = np.floor(xi[:, a])
+            off = f32(xi[:, a] - fl)
+            up = off >= 1.0                 # rounded up to the next cell edge
+            fl = np.where(up, fl + 1.0, fl)
+            off = np.where(up, 0.0, off)
+            xi[:, a] = np.mod(fl, self.grid.n[a]) + off
+        self.u[k][lo:hi] = f32(self.u[k][lo:hi])
+        self.s[k][lo:hi] = f32(self.s[k][lo:hi])
 
     def push_species(self, k, lo, hi, deposit_current=True):
         """Gather, Boris, T-BMT, move and deposit for particles lo:hi of species k."""
@@ -398,6 +422,8 @@ class Sim:
             gamma = np.sqrt(1.0 + np.sum(u_new * u_new, axis=1))
             deposit(self.J, xi, xi_new, Z * self.w[k][lo:hi], u_new[:, 2] / gamma, g)
         self.xi[k][lo:hi] = wrap(xi_new, g)
+        if self.store_fp32:
+            self._round_fp32(k, lo, hi)
 
     def step(self, nsteps=1):
         for _ in range(nsteps):

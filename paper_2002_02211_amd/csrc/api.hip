@@ -1,0 +1,1030 @@
+// Host runtime and C ABI of libspinpic: configuration checks, the tile-sorted
+// upload of the initial state, the per-step launch sequence, the lazy repack
+// of overflowing tiles, and the read-back calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/spinpic.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace spinpic;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Status {
+    int code = PIC_OK;
+    std::string msg;
+};
+
+Status fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    Status s;
+    s.code = code;
+    s.msg = buf;
+    return s;
+}
+
+#define HIP_OR_FAIL(expr)                                                                  \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) return fail(PIC_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+// ---------------------------------------------------------------- config
+
+struct Resolved {
+    pic_config cfg;
+    int ndim;
+    int n[3];
+    int T[3];
+    int nt[3];
+    double slack;
+    int use_acc64;
+};
+
+template <typename real, typename acc_t>
+size_t lds_need(const int T[3], int ndim) {
+    Geom g{};
+    g.ndim = ndim;
+    for (int a = 0; a < 3; ++a) g.T[a] = T[a];
+    return tile_lds_bytes<real, acc_t>(g);
+}
+
+Status resolve_config(const pic_config* cfg, const pic_state* init, Resolved& R) {
+    if (!cfg) return fail(PIC_EINVAL, "cfg is NULL");
+    R.cfg = *cfg;
+    const pic_config& c = *cfg;
+    if (c.ndim != 2 && c.ndim != 3) return fail(PIC_EINVAL, "ndim must be 2 or 3 (got %d)", c.ndim);
+    R.ndim = c.ndim;
+    const int maxn2[3] = {65535, 65535, 1};
+    const int maxn3[3] = {2047, 2047, 1023};
+    for (int a = 0; a < 3; ++a) {
+        if (a >= c.ndim) {
+            R.n[a] = 1;
+            continue;
+        }
+        const int lim = c.ndim == 2 ? maxn2[a] : maxn3[a];
+        if (c.n[a] < 1 || c.n[a] > lim)
+            return fail(PIC_EINVAL, "n[%d] = %d outside 1..%d", a, c.n[a], lim);
+        if (!(c.d[a] > 0.0) || !std::isfinite(c.d[a]))
+            return fail(PIC_EINVAL, "d[%d] must be positive and finite", a);
+        R.n[a] = c.n[a];
+    }
+    if (!(c.dt > 0.0) || !std::isfinite(c.dt)) return fail(PIC_EINVAL, "dt must be positive and finite");
+    double cour = 0.0;
+    for (int a = 0; a < c.ndim; ++a) cour += 1.0 / (c.d[a] * c.d[a]);
+    cour = c.dt * std::sqrt(cour);
+    if (!(cour < 1.0)) return fail(PIC_ECFL, "Courant number %.6f >= 1", cour);
+    if (c.precision != PIC_FP64 && c.precision != PIC_FP32_MIXED)
+        return fail(PIC_EINVAL, "unknown precision %d", c.precision);
+    if (c.nspecies < 1 || c.nspecies > PIC_MAX_SPECIES)
+        return fail(PIC_EINVAL, "nspecies must be 1..%d (got %d)", PIC_MAX_SPECIES, c.nspecies);
+    for (int s = 0; s < c.nspecies; ++s) {
+        const pic_species& sp = c.sp[s];
+        if (!(sp.mu > 0.0) || !std::isfinite(sp.mu) || !std::isfinite(sp.Z) || !std::isfinite(sp.a))
+            return fail(PIC_EINVAL, "species %d: mass must be positive, Z and a finite", s);
+    }
+    if (c.flags & ~PIC_FLAG_TEST_PARTICLE) return fail(PIC_EINVAL, "unknown flags 0x%x", c.flags);
+    if (c.deposit_acc < PIC_ACC_DEFAULT || c.deposit_acc > PIC_ACC_FP64)
+        return fail(PIC_EINVAL, "unknown deposit_acc %d", c.deposit_acc);
+    R.use_acc64 = c.precision == PIC_FP64 || c.deposit_acc == PIC_ACC_FP64;
+    if (c.slack < 0.0 || !std::isfinite(c.slack)) return fail(PIC_EINVAL, "slack must be >= 0");
+    R.slack = c.slack > 0.0 ? c.slack : 0.25;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= c.ndim) {
+            R.T[a] = 1;
+            R.nt[a] = 1;
+            continue;
+        }
+        int t = c.tile[a];
+        if (t == 0) t = c.ndim == 2 ? 16 : (c.precision == PIC_FP64 ? 6 : 8);
+        if (t < 1 || t > 64) return fail(PIC_EINVAL, "tile[%d] = %d outside 1..64", a, c.tile[a]);
+        t = std::min(t, R.n[a]);
+        R.T[a] = t;
+        R.nt[a] = (R.n[a] + t - 1) / t;
+    }
+    size_t lds;
+    if (c.precision == PIC_FP64) lds = lds_need<double, double>(R.T, c.ndim);
+    else if (R.use_acc64) lds = lds_need<float, double>(R.T, c.ndim);
+    else lds = lds_need<float, float>(R.T, c.ndim);
+    if (lds > 64 * 1024)
+        return fail(PIC_EINVAL, "tile %dx%dx%d needs %zu bytes of shared memory (max 65536)", R.T[0],
+                    R.T[1], R.T[2], lds);
+    const long long ntiles = (long long)R.nt[0] * R.nt[1] * R.nt[2];
+    if (ntiles * c.nspecies > (1LL << 30)) return fail(PIC_EINVAL, "too many tiles");
+    if (init) {
+        long long total = 0;
+        for (int s = 0; s < c.nspecies; ++s) {
+            if (init->count[s] < 0) return fail(PIC_EINVAL, "species %d: negative count", s);
+            if (init->count[s] > 0 && !init->particles[s])
+                return fail(PIC_EINVAL, "species %d: particles pointer is NULL", s);
+            total += init->count[s];
+        }
+        if (total > (1LL << 30)) return fail(PIC_EINVAL, "more than 2^30 particles");
+    }
+    return Status{};
+}
+
+// ---------------------------------------------------------------- engine
+
+constexpr int kTimers = 4;   // push+deposit, overflow push, insertion, field update
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
+    size_t used = 0;
+};
+
+class EngineBase {
+public:
+    virtual ~EngineBase() {}
+    virtual Status init(const Resolved& R, const pic_state* st) = 0;
+    virtual Status step(int n) = 0;
+    virtual Status polarization(int species, double emin, double emax, double P[3], int64_t* N) = 0;
+    virtual Status fields(uint32_t mask, double* out, size_t cap) = 0;
+    virtual Status particles(int species, double* out, size_t cap, int64_t* n) = 0;
+    virtual Status energy(double* out, int cap) = 0;
+    virtual Status stats(int64_t* out, int cap) = 0;
+    virtual Status timing(int enable) = 0;
+    virtual Status timing_read(double* ms, int64_t* launches, int cap) = 0;
+    virtual void release() = 0;
+};
+
+template <typename real, int DIM>
+class Engine : public EngineBase {
+public:
+    Engine(const pic_allocator* alloc, hipStream_t stream) : stream_(stream) {
+        if (alloc && alloc->alloc && alloc->free) {
+            alloc_ = *alloc;
+            has_alloc_ = true;
+        }
+    }
+    ~Engine() override { release(); }
+
+    Status init(const Resolved& R, const pic_state* st) override;
+    Status step(int n) override;
+    Status polarization(int species, double emin, double emax, double P[3], int64_t* N) override;
+    Status fields(uint32_t mask, double* out, size_t cap) override;
+    Status particles(int species, double* out, size_t cap, int64_t* n) override;
+    Status energy(double* out, int cap) override;
+    Status stats(int64_t* out, int cap) override;
+    Status timing(int enable) override;
+    Status timing_read(double* ms, int64_t* launches, int cap) override;
+    void release() override;
+
+private:
+    // device memory
+    void* dalloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void* p = nullptr;
+        if (has_alloc_) p = alloc_.alloc(alloc_.user, bytes);
+        else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+        if (p) live_.push_back(p);
+        return p;
+    }
+    void dfree(void* p) {
+        if (!p) return;
+        auto it = std::find(live_.begin(), live_.end(), p);
+        if (it != live_.end()) live_.erase(it);
+        if (has_alloc_) alloc_.free(alloc_.user, p);
+        else (void)hipFree(p);
+    }
+    Status alloc_store(PArrays<real>& a, long long cap, bool with_species);
+    void free_store(PArrays<real>& a);
+    Status repack();
+    Status reduce(int mode, const ReduceArgs& ra, double* host_acc);
+    Status compute_rho();
+    Status residual_max(double* out);
+    void tstart(int k);
+    void tstop(int k);
+    Status sync() {
+        HIP_OR_FAIL(hipStreamSynchronize(stream_));
+        return Status{};
+    }
+
+    pic_allocator alloc_{};
+    bool has_alloc_ = false;
+    hipStream_t stream_;
+    std::vector<void*> live_;
+
+    Resolved R_{};
+    Geom g_{};
+    Consts<real> k_{};
+    int deposit_ = 1;
+    int use_acc64_ = 0;
+    int nseg_ = 0;
+    long long cap_total_ = 0;
+    long long npart_ = 0;
+    long long count_sp_[kMaxSpecies] = {0, 0, 0, 0};
+    double d_[3] = {1, 1, 1};
+    int64_t nstep_ = 0;
+    int64_t repacks_ = 0;
+
+    PArrays<real> p_{}, lv_{}, st_{};
+    Segs seg_{};
+    Fields<freal> f_{};
+    Consts<freal> kf_{};          // field-update constants in the field type
+    int32_t* ctr_ = nullptr;
+    unsigned long long* moved_ = nullptr;
+    int32_t* h_ctr_ = nullptr;     // pinned mirror of the counters
+    double* acc_ = nullptr;        // reduction accumulators
+    double* rho_ = nullptr;
+    double* ref_ = nullptr;        // div E - rho at init
+    double* blockmax_ = nullptr;
+    int resid_blocks_ = 0;
+    int32_t* nf_flag_ = nullptr;
+    freal* jbuf_[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int jcur_ = 0;                 // buffer holding the last step's current
+    Timer timer_;
+};
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::alloc_store(PArrays<real>& a, long long cap, bool with_species) {
+    a = PArrays<real>{};
+    const size_t n = (size_t)std::max(cap, 1LL);
+    a.cell = (int32_t*)dalloc(n * sizeof(int32_t));
+    for (int d = 0; d < DIM; ++d) a.off[d] = (real*)dalloc(n * sizeof(real));
+    for (int d = 0; d < 3; ++d) {
+        a.u[d] = (real*)dalloc(n * sizeof(real));
+        a.s[d] = (real*)dalloc(n * sizeof(real));
+    }
+    a.w = (real*)dalloc(n * sizeof(real));
+    a.id = (int32_t*)dalloc(n * sizeof(int32_t));
+    if (with_species) a.sp = (int32_t*)dalloc(n * sizeof(int32_t));
+    bool ok = a.cell && a.w && a.id && (!with_species || a.sp);
+    for (int d = 0; d < DIM; ++d) ok = ok && a.off[d];
+    for (int d = 0; d < 3; ++d) ok = ok && a.u[d] && a.s[d];
+    if (!ok) return fail(PIC_ENOMEM, "device allocation of a particle store (%lld slots) failed", cap);
+    return Status{};
+}
+
+template <typename real, int DIM>
+void Engine<real, DIM>::free_store(PArrays<real>& a) {
+    dfree(a.cell);
+    for (int d = 0; d < 3; ++d) {
+        dfree(a.off[d]);
+        dfree(a.u[d]);
+        dfree(a.s[d]);
+    }
+    dfree(a.w);
+    dfree(a.id);
+    dfree(a.sp);
+    a = PArrays<real>{};
+}
+
+template <typename real, int DIM>
+void Engine<real, DIM>::release() {
+    if (stream_ != nullptr || !live_.empty()) (void)hipStreamSynchronize(stream_);
+    for (auto& e : timer_.pool) (void)hipEventDestroy(e);
+    timer_.pool.clear();
+    timer_.rec.clear();
+    std::vector<void*> all = live_;
+    for (void* p : all) dfree(p);
+    live_.clear();
+    if (h_ctr_) (void)hipHostFree(h_ctr_);
+    h_ctr_ = nullptr;
+}
+
+static long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+static long long seg_capacity(long long count, double slack) {
+    return round_up((long long)std::ceil(count * (1.0 + slack)) + 32, 32);
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
+    R_ = R;
+    const pic_config& c = R.cfg;
+    g_.ndim = DIM;
+    g_.nsp = c.nspecies;
+    for (int a = 0; a < 3; ++a) {
+        g_.n[a] = R.n[a];
+        g_.T[a] = R.T[a];
+        g_.nt[a] = R.nt[a];
+        d_[a] = a < DIM ? c.d[a] : 1.0;
+    }
+    g_.ntiles = g_.nt[0] * g_.nt[1] * g_.nt[2];
+    g_.ncells = (long long)g_.n[0] * g_.n[1] * g_.n[2];
+    nseg_ = g_.ntiles * g_.nsp;
+    deposit_ = (c.flags & PIC_FLAG_TEST_PARTICLE) ? 0 : 1;
+    use_acc64_ = R.use_acc64;
+
+    const double dt = c.dt;
+    k_.dt = (real)dt;
+    kf_.dt = dt;
+    for (int a = 0; a < 3; ++a) {
+        k_.dt_d[a] = (real)(dt / d_[a]);
+        k_.d_dt[a] = (real)(d_[a] / dt);
+        kf_.cb[a] = 0.5 * dt / d_[a];
+        kf_.ce[a] = dt / d_[a];
+    }
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        const bool on = s < c.nspecies;
+        const double r = on ? c.sp[s].Z / c.sp[s].mu : 0.0;
+        k_.r[s] = (real)r;
+        k_.eps[s] = (real)(0.5 * r * dt);
+        k_.a[s] = on ? (real)c.sp[s].a : real(0);
+        k_.Z[s] = on ? (real)c.sp[s].Z : real(0);
+    }
+
+    // ---- bin the initial particles by (tile, species) on the host
+    std::vector<long long> count(nseg_, 0);
+    npart_ = 0;
+    for (int s = 0; s < c.nspecies; ++s) {
+        count_sp_[s] = st ? st->count[s] : 0;
+        npart_ += count_sp_[s];
+    }
+    struct Placed {
+        int cell[3];
+        double off[3];
+    };
+    auto place = [&](const double* row, Placed& pl) -> bool {
+        for (int a = 0; a < 3; ++a) {
+            pl.cell[a] = 0;
+            pl.off[a] = 0.0;
+        }
+        for (int a = 0; a < DIM; ++a) {
+            const double xi = row[a] / d_[a];
+            if (!std::isfinite(xi)) return false;
+            const double fl = std::floor(xi);
+            double off = xi - fl;
+            long long ci = (long long)fl % g_.n[a];
+            if (ci < 0) ci += g_.n[a];
+            if ((real)off >= real(1)) {   // rounds up to the next cell edge
+                off = 0.0;
+                ci = (ci + 1) % g_.n[a];
+            }
+            pl.cell[a] = (int)ci;
+            pl.off[a] = off;
+        }
+        return true;
+    };
+    auto tile_of = [&](const Placed& pl) {
+        return pl.cell[0] / g_.T[0] + g_.nt[0] * (pl.cell[1] / g_.T[1] + g_.nt[1] * (pl.cell[2] / g_.T[2]));
+    };
+    // Within a segment the particles are interleaved across cells: first one
+    // particle of every cell, then a second one, and so on.  The lanes of a
+    // wavefront then sit in different cells, so their current deposits hit
+    // different shared-memory words instead of serializing on one.
+    const int tile_cells = g_.T[0] * g_.T[1] * g_.T[2];
+    std::vector<int32_t> segof((size_t)npart_);
+    std::vector<uint32_t> key((size_t)npart_);
+    {
+        std::vector<int32_t> cellrank((size_t)c.nspecies * g_.ncells, 0);
+        long long q = 0;
+        for (int s = 0; s < c.nspecies; ++s) {
+            const double* P = st ? st->particles[s] : nullptr;
+            for (long long i = 0; i < count_sp_[s]; ++i, ++q) {
+                const double* row = P + i * PIC_PARTICLE_IN_COLS;
+                for (int col = 0; col < PIC_PARTICLE_IN_COLS; ++col)
+                    if (!std::isfinite(row[col]))
+                        return fail(PIC_EINVAL, "species %d particle %lld: non-finite input", s, i);
+                const double s2 = row[6] * row[6] + row[7] * row[7] + row[8] * row[8];
+                if (std::fabs(s2 - 1.0) > 1e-6)
+                    return fail(PIC_EINVAL, "species %d particle %lld: |s| = %.9f, must be 1", s, i,
+                                std::sqrt(s2));
+                Placed pl;
+                place(row, pl);
+                const int sid = tile_of(pl) * c.nspecies + s;
+                segof[q] = sid;
+                count[sid]++;
+                const long long gcell = ((long long)pl.cell[2] * g_.n[1] + pl.cell[1]) * g_.n[0] + pl.cell[0];
+                const long long rank = cellrank[(size_t)s * g_.ncells + gcell]++;
+                const int lc = (pl.cell[0] % g_.T[0]) +
+                               g_.T[0] * ((pl.cell[1] % g_.T[1]) + g_.T[1] * (pl.cell[2] % g_.T[2]));
+                const unsigned long long k64 = (unsigned long long)rank * tile_cells + lc;
+                if (k64 > 0xFFFFFFFFull) return fail(PIC_EINVAL, "more than 2^32 particle ranks in a tile");
+                key[q] = (uint32_t)k64;
+            }
+        }
+    }
+    std::vector<int32_t> h_start(nseg_), h_cap(nseg_), h_count(nseg_);
+    cap_total_ = 0;
+    for (int s = 0; s < nseg_; ++s) {
+        const long long cp = seg_capacity(count[s], R.slack);
+        h_start[s] = (int32_t)cap_total_;
+        h_cap[s] = (int32_t)cp;
+        h_count[s] = (int32_t)count[s];
+        cap_total_ += cp;
+        if (cap_total_ > (1LL << 31) - 1) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^31 slots");
+    }
+
+    // ---- device allocations
+    Status S = alloc_store(p_, cap_total_, false);
+    if (S.code) return S;
+    S = alloc_store(lv_, std::max(npart_, 1LL), true);
+    if (S.code) return S;
+    S = alloc_store(st_, std::max(npart_, 1LL), true);
+    if (S.code) return S;
+    seg_.start = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    seg_.cap = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    seg_.count = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    seg_.holes = (int32_t*)dalloc(cap_total_ * sizeof(int32_t));
+    seg_.srclist = (int32_t*)dalloc(cap_total_ * sizeof(int32_t));
+    seg_.slotflag = (uint8_t*)dalloc(cap_total_);
+    for (int a = 0; a < 3; ++a) {
+        f_.E[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
+        f_.B[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
+        for (int b = 0; b < 2; ++b) jbuf_[b][a] = (freal*)dalloc(g_.ncells * sizeof(freal));
+        f_.J[a] = jbuf_[0][a];
+    }
+    ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
+    moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
+    acc_ = (double*)dalloc(8 * sizeof(double));
+    rho_ = (double*)dalloc(g_.ncells * sizeof(double));
+    ref_ = (double*)dalloc(g_.ncells * sizeof(double));
+    resid_blocks_ = (int)std::min<long long>(4096, (g_.ncells + kBlock - 1) / kBlock);
+    blockmax_ = (double*)dalloc(resid_blocks_ * sizeof(double));
+    nf_flag_ = (int32_t*)dalloc(sizeof(int32_t));
+    bool ok = seg_.start && seg_.cap && seg_.count && seg_.holes && seg_.srclist &&
+              seg_.slotflag && ctr_ && moved_ && acc_ && rho_ && ref_ && blockmax_ && nf_flag_;
+    for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
+    if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
+    HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
+    std::memset(h_ctr_, 0, CTR_NCTR * sizeof(int32_t));
+
+    // ---- upload particles in segment order
+    {
+        const size_t C = (size_t)cap_total_;
+        std::vector<int32_t> hcell(C, 0), hid(C, 0);
+        std::vector<real> hoff[3], hu[3], hs[3], hw(C, real(0));
+        for (int a = 0; a < 3; ++a) {
+            if (a < DIM) hoff[a].assign(C, real(0));
+            hu[a].assign(C, real(0));
+            hs[a].assign(C, real(0));
+        }
+        // particles of each segment in key order
+        std::vector<uint32_t> perm((size_t)npart_);
+        {
+            std::vector<long long> fill(nseg_, 0);
+            std::vector<long long> first(nseg_ + 1, 0);
+            for (int sg = 0; sg < nseg_; ++sg) first[sg + 1] = first[sg] + count[sg];
+            for (long long q = 0; q < npart_; ++q) perm[first[segof[q]] + fill[segof[q]]++] = (uint32_t)q;
+            for (int sg = 0; sg < nseg_; ++sg)
+                std::sort(perm.begin() + first[sg], perm.begin() + first[sg + 1],
+                          [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+            for (int sg = 0; sg < nseg_; ++sg) fill[sg] = 0;
+            std::vector<long long> spbase(c.nspecies + 1, 0);
+            for (int s = 0; s < c.nspecies; ++s) spbase[s + 1] = spbase[s] + count_sp_[s];
+            for (int sg = 0; sg < nseg_; ++sg) {
+                const int s = sg % c.nspecies;
+                const double* P = st ? st->particles[s] : nullptr;
+                for (long long m = first[sg]; m < first[sg + 1]; ++m) {
+                    const long long q = perm[m];
+                    const long long i = q - spbase[s];
+                    const double* row = P + i * PIC_PARTICLE_IN_COLS;
+                    Placed pl;
+                    place(row, pl);
+                    const long long slot = h_start[sg] + fill[sg]++;
+                    hcell[slot] = pack_cell<DIM>(pl.cell[0], pl.cell[1], pl.cell[2]);
+                    for (int a = 0; a < DIM; ++a) hoff[a][slot] = (real)pl.off[a];
+                    for (int a = 0; a < 3; ++a) {
+                        hu[a][slot] = (real)row[3 + a];
+                        hs[a][slot] = (real)row[6 + a];
+                    }
+                    hw[slot] = (real)row[9];
+                    hid[slot] = (int32_t)i;
+                }
+            }
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(p_.cell, hcell.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+        HIP_OR_FAIL(hipMemcpyAsync(p_.id, hid.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+        HIP_OR_FAIL(hipMemcpyAsync(p_.w, hw.data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+        for (int a = 0; a < 3; ++a) {
+            if (a < DIM)
+                HIP_OR_FAIL(hipMemcpyAsync(p_.off[a], hoff[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+            HIP_OR_FAIL(hipMemcpyAsync(p_.u[a], hu[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+            HIP_OR_FAIL(hipMemcpyAsync(p_.s[a], hs[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+        }
+        HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, h_start.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, h_cap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.count, h_count.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemsetAsync(seg_.slotflag, 0, (size_t)cap_total_, stream_));
+    HIP_OR_FAIL(hipMemsetAsync(ctr_, 0, CTR_NCTR * sizeof(int32_t), stream_));
+    HIP_OR_FAIL(hipMemsetAsync(moved_, 0, sizeof(unsigned long long), stream_));
+
+    // ---- fields
+    {
+        const size_t N = (size_t)g_.ncells;
+        for (int comp = 0; comp < 6; ++comp) {
+            freal* dst = comp < 3 ? f_.E[comp] : f_.B[comp - 3];
+            if (st && st->fields) {
+                const double* src = st->fields + comp * N;
+                for (size_t i = 0; i < N; ++i)
+                    if (!std::isfinite(src[i])) return fail(PIC_EINVAL, "field component %d: non-finite value", comp);
+                HIP_OR_FAIL(hipMemcpyAsync(dst, src, N * sizeof(freal), hipMemcpyHostToDevice, stream_));
+                HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            } else {
+                HIP_OR_FAIL(hipMemsetAsync(dst, 0, N * sizeof(freal), stream_));
+            }
+        }
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 3; ++a) HIP_OR_FAIL(hipMemsetAsync(jbuf_[b][a], 0, N * sizeof(freal), stream_));
+    }
+
+    // ---- reference residual div E - rho at t = 0
+    S = compute_rho();
+    if (S.code) return S;
+    Vec3d inv;
+    for (int a = 0; a < 3; ++a) inv.v[a] = 1.0 / d_[a];
+    HIP_OR_FAIL((launch_div_residual<freal, DIM>(g_, inv, f_, rho_, ref_, ref_, blockmax_, resid_blocks_, stream_)));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    return Status{};
+}
+
+template <typename real, int DIM>
+void Engine<real, DIM>::tstart(int k) {
+    if (!timer_.on) return;
+    if (timer_.used + 2 > timer_.pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) == hipSuccess) timer_.pool.push_back(e);
+        }
+    }
+    if (timer_.used + 2 > timer_.pool.size()) return;
+    hipEvent_t a = timer_.pool[timer_.used++];
+    hipEvent_t b = timer_.pool[timer_.used++];
+    (void)hipEventRecord(a, stream_);
+    timer_.rec.push_back({k, {a, b}});
+}
+
+template <typename real, int DIM>
+void Engine<real, DIM>::tstop(int k) {
+    if (!timer_.on || timer_.rec.empty() || timer_.rec.back().first != k) return;
+    (void)hipEventRecord(timer_.rec.back().second.second, stream_);
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::step(int nsteps) {
+    for (int it = 0; it < nsteps; ++it) {
+        // lazily fold the overflow store back into the tiles; the pinned
+        // mirror may lag the GPU by a few steps, which only delays this
+        if ((nstep_ & 63) == 0 && h_ctr_[CTR_STASH] > 0) {
+            Status S = repack();
+            if (S.code) return S;
+        }
+        const int slot = (int)(nstep_ & 1);
+        // this step deposits into the zeroed buffer; the field update zeroes
+        // the previous step's buffer behind it
+        const int jnext = jcur_ ^ 1;
+        for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jnext][a];
+        tstart(0);
+        if (use_acc64_)
+            HIP_OR_FAIL((launch_push_tiles<real, double, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
+        else
+            HIP_OR_FAIL((launch_push_tiles<real, real, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
+        tstop(0);
+        tstart(1);
+        HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, 64, stream_)));
+        tstop(1);
+        tstart(2);
+        HIP_OR_FAIL((launch_insert<real, DIM>(g_, p_, seg_, lv_, st_, ctr_, slot, moved_, 1024, stream_)));
+        tstop(2);
+        if (deposit_) {
+            tstart(3);
+            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_e<freal, DIM>(g_, kf_, f_, jbuf_[jcur_], stream_)));
+            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, stream_)));
+            tstop(3);
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, stream_));
+        if (deposit_) jcur_ = jnext;
+        for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
+        ++nstep_;
+    }
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::repack() {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
+    h_ctr_[CTR_STASH] = nst;
+    if (nst == 0) return Status{};
+    std::vector<int32_t> cnt(nseg_), old_start(nseg_);
+    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(old_start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> scell(nst), ssp(nst);
+    HIP_OR_FAIL(hipMemcpy(scell.data(), st_.cell, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(ssp.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<long long> want(cnt.begin(), cnt.end());
+    for (int i = 0; i < nst; ++i) {
+        int c[3];
+        unpack_cell<DIM>(scell[i], c[0], c[1], c[2]);
+        const int tile = c[0] / g_.T[0] + g_.nt[0] * (c[1] / g_.T[1] + g_.nt[1] * (c[2] / g_.T[2]));
+        want[tile * g_.nsp + ssp[i]]++;
+    }
+    std::vector<int32_t> nstart(nseg_), ncap(nseg_);
+    long long total = 0;
+    for (int s = 0; s < nseg_; ++s) {
+        const long long cp = seg_capacity(want[s], R_.slack);
+        nstart[s] = (int32_t)total;
+        ncap[s] = (int32_t)cp;
+        total += cp;
+        if (total > (1LL << 31) - 1) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^31 slots");
+    }
+    PArrays<real> np{};
+    Status S = alloc_store(np, total, false);
+    if (S.code) return S;
+    int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    int32_t* holes = (int32_t*)dalloc(total * sizeof(int32_t));
+    int32_t* srcl = (int32_t*)dalloc(total * sizeof(int32_t));
+    uint8_t* flags = (uint8_t*)dalloc(total);
+    if (!d_nstart || !holes || !srcl || !flags) return fail(PIC_ENOMEM, "repack allocation failed");
+    HIP_OR_FAIL(hipMemcpyAsync(d_nstart, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL((launch_repack_segments<real>(p_, np, seg_.start, d_nstart, seg_.count, nseg_, DIM, stream_)));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, ncap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemsetAsync(flags, 0, (size_t)total, stream_));
+    // move the overflow particles into their tiles: the insertion kernel run
+    // over the overflow store, which now always finds room
+    HIP_OR_FAIL((launch_insert<real, DIM>(g_, np, seg_, st_, st_, ctr_, CTR_STASH, moved_, 256, stream_)));
+    HIP_OR_FAIL(hipMemsetAsync(ctr_ + CTR_STASH, 0, sizeof(int32_t), stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    free_store(p_);
+    dfree(seg_.holes);
+    dfree(seg_.srclist);
+    dfree(seg_.slotflag);
+    dfree(d_nstart);
+    p_ = np;
+    seg_.holes = holes;
+    seg_.srclist = srcl;
+    seg_.slotflag = flags;
+    cap_total_ = total;
+    h_ctr_[CTR_STASH] = 0;
+    repacks_++;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::reduce(int mode, const ReduceArgs& ra, double* host_acc) {
+    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+    HIP_OR_FAIL((launch_reduce_particles<real, DIM>(mode, g_, p_, seg_, st_, ctr_, ra, acc_, rho_, stream_)));
+    HIP_OR_FAIL(hipMemcpyAsync(host_acc, acc_, 8 * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::compute_rho() {
+    ReduceArgs ra{};
+    ra.species = -1;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        ra.mu[s] = s < g_.nsp ? R_.cfg.sp[s].mu : 1.0;
+        ra.Z[s] = s < g_.nsp ? R_.cfg.sp[s].Z : 0.0;
+    }
+    HIP_OR_FAIL(hipMemsetAsync(rho_, 0, g_.ncells * sizeof(double), stream_));
+    HIP_OR_FAIL((launch_reduce_particles<real, DIM>(RED_RHO, g_, p_, seg_, st_, ctr_, ra, acc_, rho_, stream_)));
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::polarization(int species, double emin, double emax, double P[3], int64_t* N) {
+    if (species < -1 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (std::isnan(emin) || std::isnan(emax)) return fail(PIC_EINVAL, "energy window is NaN");
+    ReduceArgs ra{};
+    ra.species = species;
+    ra.emin = emin;
+    ra.emax = emax;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        ra.mu[s] = s < g_.nsp ? R_.cfg.sp[s].mu : 1.0;
+        ra.Z[s] = s < g_.nsp ? R_.cfg.sp[s].Z : 0.0;
+    }
+    double acc[8];
+    Status S = reduce(RED_POLARIZATION, ra, acc);
+    if (S.code) return S;
+    const double n = acc[3];
+    *N = (int64_t)std::llround(n);
+    for (int a = 0; a < 3; ++a) P[a] = n > 0 ? acc[a] / n : 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(P[a])) return fail(PIC_ENONFINITE, "polarization is not finite");
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::fields(uint32_t mask, double* out, size_t cap) {
+    if (mask & ~0x3FFu) return fail(PIC_EINVAL, "unknown field mask bits 0x%x", mask);
+    const size_t N = (size_t)g_.ncells;
+    int nc = 0;
+    for (int b = 0; b < 10; ++b) nc += (mask >> b) & 1;
+    if (!out && nc) return fail(PIC_EINVAL, "host_out is NULL");
+    if (cap < (size_t)nc * N) return fail(PIC_EINVAL, "cap %zu < %zu", cap, (size_t)nc * N);
+    if (mask & PIC_RHO) {
+        Status S = compute_rho();
+        if (S.code) return S;
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    size_t o = 0;
+    for (int b = 0; b < 10; ++b) {
+        if (!((mask >> b) & 1)) continue;
+        const freal* src = b == 9 ? rho_ : (b < 3 ? f_.E[b] : (b < 6 ? f_.B[b - 3] : f_.J[b - 6]));
+        HIP_OR_FAIL(hipMemcpy(out + o, src, N * sizeof(freal), hipMemcpyDeviceToHost));
+        o += N;
+    }
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_t* n_out) {
+    if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    const long long n = count_sp_[species];
+    if (n_out) *n_out = n;
+    if (cap < (size_t)n * PIC_PARTICLE_OUT_COLS) return fail(PIC_EINVAL, "cap too small for %lld particles", n);
+    if (n > 0 && !out) return fail(PIC_EINVAL, "host_out is NULL");
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    std::vector<int32_t> start(nseg_), count(nseg_);
+    HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(count.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<char> seen((size_t)n, 0);
+    // read one store into host vectors and emit the rows of this species
+    auto emit = [&](const PArrays<real>& A, long long len, const std::vector<std::pair<long long, long long>>& ranges,
+                    bool stash) -> Status {
+        if (len == 0) return Status{};
+        std::vector<int32_t> cell(len), id(len), sp;
+        std::vector<real> off[3], u[3], s[3], w(len);
+        HIP_OR_FAIL(hipMemcpy(cell.data(), A.cell, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(id.data(), A.id, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(w.data(), A.w, len * sizeof(real), hipMemcpyDeviceToHost));
+        if (stash) {
+            sp.resize(len);
+            HIP_OR_FAIL(hipMemcpy(sp.data(), A.sp, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (a < DIM) {
+                off[a].resize(len);
+                HIP_OR_FAIL(hipMemcpy(off[a].data(), A.off[a], len * sizeof(real), hipMemcpyDeviceToHost));
+            }
+            u[a].resize(len);
+            s[a].resize(len);
+            HIP_OR_FAIL(hipMemcpy(u[a].data(), A.u[a], len * sizeof(real), hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(hipMemcpy(s[a].data(), A.s[a], len * sizeof(real), hipMemcpyDeviceToHost));
+        }
+        for (const auto& r : ranges)
+            for (long long q = r.first; q < r.second; ++q) {
+                if (stash && sp[q] != species) continue;
+                const long long i = id[q];
+                if (i < 0 || i >= n || seen[i]) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (id %lld)", i);
+                seen[i] = 1;
+                double* row = out + i * PIC_PARTICLE_OUT_COLS;
+                int c[3];
+                unpack_cell<DIM>(cell[q], c[0], c[1], c[2]);
+                row[0] = (double)i;
+                for (int a = 0; a < 3; ++a) row[1 + a] = a < DIM ? ((double)c[a] + (double)off[a][q]) * d_[a] : 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    row[4 + a] = (double)u[a][q];
+                    row[7 + a] = (double)s[a][q];
+                }
+                row[10] = (double)w[q];
+            }
+        return Status{};
+    };
+    std::vector<std::pair<long long, long long>> ranges;
+    for (int t = 0; t < g_.ntiles; ++t) {
+        const int sid = t * g_.nsp + species;
+        ranges.push_back({start[sid], (long long)start[sid] + count[sid]});
+    }
+    Status S = emit(p_, cap_total_, ranges, false);
+    if (S.code) return S;
+    S = emit(st_, nst, {{0, (long long)nst}}, true);
+    if (S.code) return S;
+    for (long long i = 0; i < n; ++i)
+        if (!seen[i]) return fail(PIC_ESTATE, "particle %lld of species %d is missing", i, species);
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::residual_max(double* out) {
+    Status S = compute_rho();
+    if (S.code) return S;
+    Vec3d inv;
+    for (int a = 0; a < 3; ++a) inv.v[a] = 1.0 / d_[a];
+    HIP_OR_FAIL((launch_div_residual<freal, DIM>(g_, inv, f_, rho_, ref_, nullptr, blockmax_, resid_blocks_, stream_)));
+    std::vector<double> h(resid_blocks_);
+    HIP_OR_FAIL(hipMemcpyAsync(h.data(), blockmax_, resid_blocks_ * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    double m = 0.0;
+    for (double v : h) m = std::max(m, v);
+    *out = m;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::energy(double* out, int cap) {
+    if (!out || cap < g_.nsp + 2) return fail(PIC_EINVAL, "energy needs cap >= %d", g_.nsp + 2);
+    double V = 1.0;
+    for (int a = 0; a < DIM; ++a) V *= d_[a];
+    ReduceArgs ra{};
+    ra.species = -1;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        ra.mu[s] = s < g_.nsp ? R_.cfg.sp[s].mu : 1.0;
+        ra.Z[s] = s < g_.nsp ? R_.cfg.sp[s].Z : 0.0;
+    }
+    double acc[8];
+    Status S = reduce(RED_KINETIC, ra, acc);
+    if (S.code) return S;
+    for (int s = 0; s < g_.nsp; ++s) out[s] = acc[s] * V;
+    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+    HIP_OR_FAIL((launch_field_energy<freal>(g_, f_, acc_, stream_)));
+    HIP_OR_FAIL(hipMemcpyAsync(acc, acc_, sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    out[g_.nsp] = acc[0] * V;
+    S = residual_max(&out[g_.nsp + 1]);
+    if (S.code) return S;
+    for (int i = 0; i < g_.nsp + 2; ++i)
+        if (!std::isfinite(out[i])) return fail(PIC_ENONFINITE, "energy diagnostic %d is not finite", i);
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::stats(int64_t* out, int cap) {
+    if (!out || cap < 5) return fail(PIC_EINVAL, "stats needs cap >= 5");
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    unsigned long long moved = 0;
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&moved, moved_, sizeof moved, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    out[0] = nstep_;
+    out[1] = (int64_t)moved;
+    out[2] = nst;
+    out[3] = repacks_;
+    out[4] = npart_;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::timing(int enable) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    timer_.on = enable != 0;
+    timer_.rec.clear();
+    timer_.used = 0;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::timing_read(double* ms, int64_t* launches, int cap) {
+    if (cap < kTimers) return fail(PIC_EINVAL, "timing_read needs cap >= %d", kTimers);
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    double t[kTimers] = {0, 0, 0, 0};
+    int64_t c[kTimers] = {0, 0, 0, 0};
+    for (auto& r : timer_.rec) {
+        float e = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&e, r.second.first, r.second.second));
+        t[r.first] += e;
+        c[r.first]++;
+    }
+    for (int i = 0; i < kTimers; ++i) {
+        if (ms) ms[i] = t[i];
+        if (launches) launches[i] = c[i];
+    }
+    return Status{};
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+struct pic_ctx {
+    std::unique_ptr<EngineBase> eng;
+    std::string err;
+    bool failed = false;
+};
+
+static int finish(pic_ctx* ctx, const Status& s) {
+    if (s.code != PIC_OK) {
+        ctx->err = s.msg;
+        if (s.code == PIC_EHIP || s.code == PIC_ESTATE) ctx->failed = true;
+    }
+    return s.code;
+}
+
+#define CTX_CHECK(ctx)                                        \
+    do {                                                      \
+        if (!(ctx)) return PIC_ESTATE;                        \
+        if ((ctx)->failed || !(ctx)->eng) {                   \
+            (ctx)->err = "context is unusable after an error"; \
+            return PIC_ESTATE;                                \
+        }                                                     \
+    } while (0)
+
+extern "C" {
+
+int pic_init(const pic_config* cfg, const pic_state* init, const pic_allocator* alloc,
+             void* hip_stream, pic_ctx** out) {
+    g_init_error.clear();
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PIC_EINVAL;
+    }
+    *out = nullptr;
+    Resolved R;
+    Status s = resolve_config(cfg, init, R);
+    if (s.code) {
+        g_init_error = s.msg;
+        return s.code;
+    }
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        g_init_error = "allocator needs both alloc and free";
+        return PIC_EINVAL;
+    }
+    std::unique_ptr<EngineBase> eng;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (cfg->precision == PIC_FP64) {
+        if (cfg->ndim == 2) eng.reset(new Engine<double, 2>(alloc, stream));
+        else eng.reset(new Engine<double, 3>(alloc, stream));
+    } else {
+        if (cfg->ndim == 2) eng.reset(new Engine<float, 2>(alloc, stream));
+        else eng.reset(new Engine<float, 3>(alloc, stream));
+    }
+    s = eng->init(R, init);
+    if (s.code) {
+        g_init_error = s.msg;
+        eng->release();
+        return s.code;
+    }
+    pic_ctx* ctx = new pic_ctx();
+    ctx->eng = std::move(eng);
+    *out = ctx;
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx* ctx, int32_t nsteps) {
+    CTX_CHECK(ctx);
+    if (nsteps < 0) {
+        ctx->err = "nsteps must be >= 0";
+        return PIC_EINVAL;
+    }
+    return finish(ctx, ctx->eng->step(nsteps));
+}
+
+int pic_polarization(pic_ctx* ctx, int32_t species, double emin, double emax, double P_out[3],
+                     int64_t* N_out) {
+    CTX_CHECK(ctx);
+    if (!P_out || !N_out) {
+        ctx->err = "P_out and N_out must not be NULL";
+        return PIC_EINVAL;
+    }
+    return finish(ctx, ctx->eng->polarization(species, emin, emax, P_out, N_out));
+}
+
+int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->fields(mask, host_out, cap_doubles));
+}
+
+int pic_particles(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles, int64_t* n_out) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->particles(species, host_out, cap_doubles, n_out));
+}
+
+int pic_energy(pic_ctx* ctx, double* out, int32_t cap) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->energy(out, cap));
+}
+
+int pic_stats(pic_ctx* ctx, int64_t* out, int32_t cap) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->stats(out, cap));
+}
+
+int pic_timing(pic_ctx* ctx, int32_t enable) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->timing(enable));
+}
+
+int pic_timing_read(pic_ctx* ctx, double* ms_out, int64_t* launches_out, int32_t cap) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->timing_read(ms_out, launches_out, cap));
+}
+
+const char* pic_last_error(const pic_ctx* ctx) {
+    if (!ctx) return g_init_error.c_str();
+    return ctx->err.c_str();
+}
+
+void pic_free(pic_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->eng) ctx->eng->release();
+    delete ctx;
+}
+
+}  // extern "C"

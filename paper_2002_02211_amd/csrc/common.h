@@ -1,0 +1,437 @@
+// Device-side building blocks of the spin-resolved PIC step (gfx950).
+//
+// Particles live in a structure of arrays, grouped in segments by
+// (tile, species).  A particle stores its cell as one packed int32 and its
+// position inside the cell as offsets in [0, 1) per axis, so FP32 keeps full
+// resolution anywhere in a large box.  Particles and the push use the type
+// `real` (float or double); the grid fields E, B, J are always double, the
+// type `freal` below: in FP32 the rounding of the large laser field would
+// accumulate step after step in the field update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spinpic {
+
+constexpr int kMaxSpecies = 4;
+constexpr int kBlock = 256;   // threads per workgroup: 4 wave64
+
+// ---------------------------------------------------------------- layout
+
+template <typename real>
+struct PArrays {
+    int32_t* cell;    // packed cell index
+    real* off[3];     // offset inside the cell along x, y, z (z unused in 2D)
+    real* u[3];       // u = gamma * beta
+    real* s[3];       // spin vector
+    real* w;          // weight (density units)
+    int32_t* id;      // row index in the initial state of its species
+    int32_t* sp;      // species (leaver and overflow stores only)
+};
+
+template <typename real>
+struct Fields {
+    real* E[3];
+    real* B[3];
+    real* J[3];
+};
+
+struct Geom {
+    int ndim;
+    int nsp;
+    int n[3];       // cells per axis (n[2] = 1 in 2D)
+    int T[3];       // tile edge per axis (T[2] = 1 in 2D)
+    int nt[3];      // tiles per axis
+    int ntiles;
+    long long ncells;
+};
+
+template <typename real>
+struct Consts {
+    real dt;
+    real dt_d[3];     // dt / d_a: displacement in cells per unit velocity
+    real d_dt[3];     // d_a / dt: Esirkepov current scale
+    real eps[kMaxSpecies];   // r dt / 2 with r = Z / mu
+    real r[kMaxSpecies];
+    real a[kMaxSpecies];
+    real Z[kMaxSpecies];
+    real cb[3];       // (dt / 2) / d_a  (B half step)
+    real ce[3];       // dt / d_a        (E step)
+};
+
+struct Segs {
+    int32_t* start;     // first slot of each (tile, species) segment
+    int32_t* cap;       // slots reserved for it
+    int32_t* count;     // particles it holds
+    int32_t* holes;     // slot indices vacated by leavers (per segment, from start)
+    int32_t* srclist;   // compaction scratch (per segment, from start)
+    uint8_t* slotflag;  // compaction scratch, one byte per slot, kept zero
+};
+
+// Device counters (int32 unless noted), cleared at init.
+enum {
+    CTR_LEAVE0 = 0,   // leavers of even steps
+    CTR_LEAVE1 = 1,   // leavers of odd steps
+    CTR_STASH = 2,    // particles in the overflow store
+    CTR_NCTR = 4
+};
+
+// ---------------------------------------------------------------- cells
+
+template <int DIM>
+__host__ __device__ inline int32_t pack_cell(int cx, int cy, int cz) {
+    if (DIM == 2) return cx | (cy << 16);
+    return cx | (cy << 11) | (cz << 22);
+}
+
+template <int DIM>
+__host__ __device__ inline void unpack_cell(int32_t c, int& cx, int& cy, int& cz) {
+    if (DIM == 2) {
+        cx = c & 0xFFFF;
+        cy = (int)((uint32_t)c >> 16);
+        cz = 0;
+    } else {
+        cx = c & 0x7FF;
+        cy = (c >> 11) & 0x7FF;
+        cz = (int)((uint32_t)c >> 22);
+    }
+}
+
+__host__ __device__ inline int wrap_index(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// ---------------------------------------------------------------- math
+
+__device__ inline float fsqrt(float x) { return sqrtf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+
+// Reciprocal and reciprocal square root of arguments >= 1.  FP64 keeps the
+// correctly rounded division and square root; FP32 uses the hardware
+// approximations v_rcp_f32 and v_rsq_f32 (about 1 ulp), well inside the
+// FP32 error budget and a fraction of the cost of IEEE division.
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float rsqrt1(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt1(double x) { return 1.0 / sqrt(x); }
+
+template <typename real>
+__device__ inline void cross(const real a[3], const real b[3], real out[3]) {
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename real>
+__device__ inline real dot3(const real a[3], const real b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// ---------------------------------------------------------------- stencils
+//
+// Along one axis a particle sits in cell l at offset o.  A component stored
+// at integer positions is interpolated from nodes l, l+1 with weight o on
+// l+1; a component stored at half-integer positions (index i holds i + 1/2)
+// from the two half points that straddle the particle.
+template <typename real>
+struct Stencil1 {
+    int li;  real fi;    // integer-staggered: first node, weight of the second
+    int lh;  real fh;    // half-staggered
+};
+
+template <typename real>
+__device__ inline Stencil1<real> stencil1(int l, real o) {
+    Stencil1<real> st;
+    st.li = l;
+    st.fi = o;
+    const bool upper = o >= real(0.5);
+    st.lh = upper ? l : l - 1;
+    st.fh = upper ? o - real(0.5) : o + real(0.5);
+    return st;
+}
+
+template <typename real>
+__device__ inline real lerp(real a, real b, real f) { return a + f * (b - a); }
+
+// Field source in the shared-memory tile: element (i, j, k) of a component
+// is the value at local cell (i, j, k), for i in -1 .. T (guard included).
+template <typename real, int DIM>
+struct TileFields {
+    const real* base;   // 6 components of G values each: Ex Ey Ez Bx By Bz
+    int Gx, Gxy, G;
+    __device__ inline const real* comp(int c, int i, int j, int k) const {
+        return base + c * G + (DIM == 3 ? (k + 1) * Gxy : 0) + (j + 1) * Gx + (i + 1);
+    }
+    __device__ inline int sx() const { return 1; }
+    __device__ inline int sy() const { return Gx; }
+    __device__ inline int sz() const { return Gxy; }
+};
+
+// Interpolate component c whose per-axis stagger is (hx, hy, hz) (1 = half).
+template <typename real, int DIM>
+__device__ inline real interp(const TileFields<real, DIM>& F, int c,
+                                   const Stencil1<real> st[3], int hx, int hy, int hz) {
+    const int i = hx ? st[0].lh : st[0].li;
+    const real fx = hx ? st[0].fh : st[0].fi;
+    const int j = hy ? st[1].lh : st[1].li;
+    const real fy = hy ? st[1].fh : st[1].fi;
+    if (DIM == 2) {
+        const real* q = F.comp(c, i, j, 0);
+        const real lo = lerp(q[0], q[1], fx);
+        const real hi = lerp(q[F.Gx], q[F.Gx + 1], fx);
+        return lerp(lo, hi, fy);
+    }
+    const int k = hz ? st[2].lh : st[2].li;
+    const real fz = hz ? st[2].fh : st[2].fi;
+    const real* q = F.comp(c, i, j, k);
+    const int Gx = F.Gx, Gxy = F.Gxy;
+    const real a0 = lerp(lerp(q[0], q[1], fx), lerp(q[Gx], q[Gx + 1], fx), fy);
+    const real a1 = lerp(lerp(q[Gxy], q[Gxy + 1], fx),
+                         lerp(q[Gxy + Gx], q[Gxy + Gx + 1], fx), fy);
+    return lerp(a0, a1, fz);
+}
+
+// Field source in global memory with periodic wrap; cells are absolute.
+template <typename freal, int DIM>
+struct GlobalFields {
+    const freal* c[6];
+    int n[3];
+    __device__ inline freal at(int comp, int i, int j, int k) const {
+        i = wrap_index(i, n[0]);
+        j = wrap_index(j, n[1]);
+        k = DIM == 3 ? wrap_index(k, n[2]) : 0;
+        return c[comp][((long long)k * n[1] + j) * n[0] + i];
+    }
+};
+
+// Values are rounded to the push precision as they are read.
+template <typename real, typename freal, int DIM>
+__device__ inline real interp(const GlobalFields<freal, DIM>& F, int c,
+                              const Stencil1<real> st[3], int hx, int hy, int hz) {
+    const int i = hx ? st[0].lh : st[0].li;
+    const real fx = hx ? st[0].fh : st[0].fi;
+    const int j = hy ? st[1].lh : st[1].li;
+    const real fy = hy ? st[1].fh : st[1].fi;
+    auto at = [&](int ii, int jj, int kk) { return (real)F.at(c, ii, jj, kk); };
+    if (DIM == 2) {
+        const real lo = lerp(at(i, j, 0), at(i + 1, j, 0), fx);
+        const real hi = lerp(at(i, j + 1, 0), at(i + 1, j + 1, 0), fx);
+        return lerp(lo, hi, fy);
+    }
+    const int k = hz ? st[2].lh : st[2].li;
+    const real fz = hz ? st[2].fh : st[2].fi;
+    const real a0 = lerp(lerp(at(i, j, k), at(i + 1, j, k), fx),
+                         lerp(at(i, j + 1, k), at(i + 1, j + 1, k), fx), fy);
+    const real a1 = lerp(lerp(at(i, j, k + 1), at(i + 1, j, k + 1), fx),
+                         lerp(at(i, j + 1, k + 1), at(i + 1, j + 1, k + 1), fx), fy);
+    return lerp(a0, a1, fz);
+}
+
+// E and B at the particle; the stagger arguments (x, y, z) follow the Yee
+// cell: E_a is half-staggered along a, B_a along the two other axes.
+template <typename real, class Src>
+__device__ inline void gather_all(const Src& F, const Stencil1<real> st[3], real E[3], real B[3]) {
+    E[0] = interp(F, 0, st, 1, 0, 0);
+    E[1] = interp(F, 1, st, 0, 1, 0);
+    E[2] = interp(F, 2, st, 0, 0, 1);
+    B[0] = interp(F, 3, st, 0, 1, 1);
+    B[1] = interp(F, 4, st, 1, 0, 1);
+    B[2] = interp(F, 5, st, 1, 1, 0);
+}
+
+// ---------------------------------------------------------------- push
+//
+// Boris push and Thomas-BMT rotation of one particle.  On entry u = u^(n-1/2),
+// s = s^(n-1/2); on exit u^(n+1/2), s^(n+1/2).
+//
+// Boris: u- = u + eps E, t = eps B / gamma-, u' = u- + u- x t,
+//        u+ = u- + 2/(1+t.t) u' x t, u^(n+1/2) = u+ + eps E, eps = r dt/2.
+// Spin (section 2 Eq. 1-3 with q/(mc) -> r, v/c -> beta): with gamma = gamma-
+// and beta = (u- + u+)/(2 gamma-),
+//   Omega = r [(a + 1/gamma) B - a gamma/(gamma+1) (beta.B) beta
+//              - (a + 1/(1+gamma)) beta x E],
+// and ds/dt = -Omega x s = s x Omega is advanced by the same rotation with
+// tau = Omega dt/2 in place of t.
+template <typename real>
+__device__ inline void boris_tbmt(real u[3], real s[3], const real E[3], const real B[3],
+                                  real eps, real r, real a, real half_dt) {
+    real um[3], t[3], up[3], tmp[3], uprime[3];
+    um[0] = u[0] + eps * E[0];
+    um[1] = u[1] + eps * E[1];
+    um[2] = u[2] + eps * E[2];
+    const real g2 = real(1) + dot3(um, um);
+    const real igm = rsqrt1(g2);
+    const real gm = g2 * igm;
+    const real ke = eps * igm;
+    t[0] = ke * B[0];
+    t[1] = ke * B[1];
+    t[2] = ke * B[2];
+    cross(um, t, tmp);
+    uprime[0] = um[0] + tmp[0];
+    uprime[1] = um[1] + tmp[1];
+    uprime[2] = um[2] + tmp[2];
+    const real sfac = real(2) * recip(real(1) + dot3(t, t));
+    cross(uprime, t, tmp);
+    up[0] = um[0] + sfac * tmp[0];
+    up[1] = um[1] + sfac * tmp[1];
+    up[2] = um[2] + sfac * tmp[2];
+
+    // Thomas-BMT precession vector at gamma-, beta = (u- + u+)/(2 gamma-)
+    real beta[3], bxe[3], Om[3], tau[3], sprime[3];
+    const real hb = real(0.5) * igm;
+    beta[0] = (um[0] + up[0]) * hb;
+    beta[1] = (um[1] + up[1]) * hb;
+    beta[2] = (um[2] + up[2]) * hb;
+    const real igp1 = recip(gm + real(1));
+    const real Omega_B = a + igm;
+    const real Omega_v = a * gm * igp1;
+    const real Omega_E = a + igp1;
+    const real bB = dot3(beta, B);
+    cross(beta, E, bxe);
+    const real kv = Omega_v * bB;
+    Om[0] = r * (Omega_B * B[0] - kv * beta[0] - Omega_E * bxe[0]);
+    Om[1] = r * (Omega_B * B[1] - kv * beta[1] - Omega_E * bxe[1]);
+    Om[2] = r * (Omega_B * B[2] - kv * beta[2] - Omega_E * bxe[2]);
+    tau[0] = half_dt * Om[0];
+    tau[1] = half_dt * Om[1];
+    tau[2] = half_dt * Om[2];
+    cross(s, tau, tmp);
+    sprime[0] = s[0] + tmp[0];
+    sprime[1] = s[1] + tmp[1];
+    sprime[2] = s[2] + tmp[2];
+    const real sf = real(2) * recip(real(1) + dot3(tau, tau));
+    cross(sprime, tau, tmp);
+    s[0] = s[0] + sf * tmp[0];
+    s[1] = s[1] + sf * tmp[1];
+    s[2] = s[2] + sf * tmp[2];
+
+    u[0] = up[0] + eps * E[0];
+    u[1] = up[1] + eps * E[1];
+    u[2] = up[2] + eps * E[2];
+}
+
+// Advance one offset by disp cells (|disp| < 1); returns the cell change
+// (-1, 0, +1) and leaves the new offset in [0, 1).  If an offset just below
+// a cell edge rounds up to 1, the particle is placed at the edge of the
+// next cell instead.
+template <typename real>
+__device__ inline int advance_offset(real& o, real disp) {
+    real x = o + disp;
+    int dc = 0;
+    if (x >= real(1)) {
+        x -= real(1);
+        dc = 1;
+    } else if (x < real(0)) {
+        x += real(1);
+        dc = -1;
+        if (x >= real(1)) {
+            x = real(0);
+            dc = 0;
+        }
+    }
+    o = x;
+    return dc;
+}
+
+// CIC shape factors before and after the move on the three nodes b, b+1, b+2
+// with b = min(old cell, new cell).  Returns b relative to the old cell
+// (0 or -1).
+template <typename real>
+__device__ inline int shape_pair(real o0, real o1, int dc, real S0[3], real S1[3]) {
+    if (dc == 0) {
+        S0[0] = real(1) - o0; S0[1] = o0; S0[2] = real(0);
+        S1[0] = real(1) - o1; S1[1] = o1; S1[2] = real(0);
+        return 0;
+    }
+    if (dc > 0) {
+        S0[0] = real(1) - o0; S0[1] = o0; S0[2] = real(0);
+        S1[0] = real(0); S1[1] = real(1) - o1; S1[2] = o1;
+        return 0;
+    }
+    S0[0] = real(0); S0[1] = real(1) - o0; S0[2] = o0;
+    S1[0] = real(1) - o1; S1[1] = o1; S1[2] = real(0);
+    return -1;
+}
+
+// Esirkepov current of one particle.  sink(c, i, j, k, v) adds v to J_c at
+// stencil node (i, j, k) relative to the base node b.  With q_a = -Z w d_a/dt,
+// J_a at b + i + 1/2 along a is q_a times the running sum of W_a over the
+// nodes up to i, so that (rho^(n+1) - rho^n)/dt + div J = 0 on every node.
+//   2D: W_x = DSx (S0y + DSy/2), W_y = (S0x + DSx/2) DSy,
+//       J_z = Z w v_z [S0x S0y + (DSx S0y + S0x DSy)/2 + DSx DSy/3].
+//   3D: W_x = DSx (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3), cyclic.
+template <typename real, int DIM, class Sink>
+__device__ inline void esirkepov(const real S0[3][3], const real S1[3][3],
+                                 const real q[3], real qz2d, Sink& sink) {
+    real DS[3][3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) DS[a][k] = S1[a][k] - S0[a][k];
+    if (DIM == 2) {
+        // J_x at (b+i+1/2, b+j): -qx * sum_{i'<=i} DSx[i'] (S0y[j] + DSy[j]/2)
+        real hy[3], hx[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            hy[k] = S0[1][k] + real(0.5) * DS[1][k];
+            hx[k] = S0[0][k] + real(0.5) * DS[0][k];
+        }
+        const real cx0 = DS[0][0];
+        const real cx1 = DS[0][0] + DS[0][1];
+        const real cy0 = DS[1][0];
+        const real cy1 = DS[1][0] + DS[1][1];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            sink(0, 0, j, 0, q[0] * cx0 * hy[j]);
+            sink(0, 1, j, 0, q[0] * cx1 * hy[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            sink(1, i, 0, 0, q[1] * hx[i] * cy0);
+            sink(1, i, 1, 0, q[1] * hx[i] * cy1);
+        }
+        const real third = real(1) / real(3);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const real wz = S0[0][i] * S0[1][j]
+                              + real(0.5) * (DS[0][i] * S0[1][j] + S0[0][i] * DS[1][j])
+                              + third * DS[0][i] * DS[1][j];
+                sink(2, i, j, 0, qz2d * wz);
+            }
+        return;
+    }
+    // 3D: per component a, weights over the two transverse axes b, c
+    const real third = real(1) / real(3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3;
+        const int c = (a + 2) % 3;
+        real T[3][3];   // transverse factor over (node of b, node of c)
+#pragma unroll
+        for (int jb = 0; jb < 3; ++jb)
+#pragma unroll
+            for (int jc = 0; jc < 3; ++jc)
+                T[jb][jc] = S0[b][jb] * S0[c][jc]
+                          + real(0.5) * (DS[b][jb] * S0[c][jc] + S0[b][jb] * DS[c][jc])
+                          + third * DS[b][jb] * DS[c][jc];
+        const real c0 = DS[a][0];
+        const real c1 = DS[a][0] + DS[a][1];
+#pragma unroll
+        for (int jb = 0; jb < 3; ++jb)
+#pragma unroll
+            for (int jc = 0; jc < 3; ++jc) {
+                int idx0[3], idx1[3];
+                idx0[a] = 0; idx1[a] = 1;
+                idx0[b] = jb; idx1[b] = jb;
+                idx0[c] = jc; idx1[c] = jc;
+                sink(a, idx0[0], idx0[1], idx0[2], q[a] * c0 * T[jb][jc]);
+                sink(a, idx1[0], idx1[1], idx1[2], q[a] * c1 * T[jb][jc]);
+            }
+    }
+}
+
+}  // namespace spinpic

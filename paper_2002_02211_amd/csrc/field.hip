@@ -1,0 +1,330 @@
+// Grid kernels: the Yee FDTD update and the FP64 diagnostics (section 2
+// Eq. 4 polarization, energies, charge density and div E - rho).
+#include "common.h"
+#include "kernels.h"
+
+namespace spinpic {
+
+constexpr int kFx = 64, kFy = 4;   // field kernels: 64 x 4 threads, x fastest
+
+// B -= (dt/2) curl E.  B_x sits at (i, j+1/2, k+1/2), B_y at (i+1/2, j, k+1/2),
+// B_z at (i+1/2, j+1/2, k); E_a at half a cell along a.  Forward differences
+// with periodic wrap.  In 2D every d/dz is zero.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_b(Geom g, Consts<real> k, Fields<real> f) {
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    const int kz = blockIdx.z;
+    const int nx = g.n[0], ny = g.n[1];
+    if (i >= nx || j >= ny) return;
+    const long long nxy = (long long)nx * ny;
+    const long long c = kz * nxy + (long long)j * nx + i;
+    const long long ip = i + 1 == nx ? c - i : c + 1;
+    const long long jp = j + 1 == ny ? c - (long long)j * nx : c + nx;
+    const real* __restrict__ Ex = f.E[0];
+    const real* __restrict__ Ey = f.E[1];
+    const real* __restrict__ Ez = f.E[2];
+    const real ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    real cx = k.cb[1] * (Ez[jp] - ez);                 // d/dy E_z
+    real cy = -k.cb[0] * (Ez[ip] - ez);                // -d/dx E_z
+    const real cz = k.cb[0] * (Ey[ip] - ey) - k.cb[1] * (Ex[jp] - ex);
+    if (DIM == 3) {
+        const long long kp = kz + 1 == g.n[2] ? c - kz * nxy : c + nxy;
+        cx -= k.cb[2] * (Ey[kp] - ey);                 // -d/dz E_y
+        cy += k.cb[2] * (Ex[kp] - ex);                 // d/dz E_x
+    }
+    f.B[0][c] -= cx;
+    f.B[1][c] -= cy;
+    f.B[2][c] -= cz;
+}
+
+// E += dt (curl B - J).  Backward differences with periodic wrap.  The
+// other current buffer, no longer needed, is zeroed here for the next
+// step's deposit (when jclear is non-NULL).
+struct JClear {
+    void* c[3];
+};
+
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    const int kz = blockIdx.z;
+    const int nx = g.n[0], ny = g.n[1];
+    if (i >= nx || j >= ny) return;
+    const long long nxy = (long long)nx * ny;
+    const long long c = kz * nxy + (long long)j * nx + i;
+    const long long im = i == 0 ? c + nx - 1 : c - 1;
+    const long long jm = j == 0 ? c + (long long)(ny - 1) * nx : c - nx;
+    const real* __restrict__ Bx = f.B[0];
+    const real* __restrict__ By = f.B[1];
+    const real* __restrict__ Bz = f.B[2];
+    const real bx = Bx[c], by = By[c], bz = Bz[c];
+    real cx = k.ce[1] * (bz - Bz[jm]);                 // d/dy B_z
+    real cy = -k.ce[0] * (bz - Bz[im]);                // -d/dx B_z
+    const real cz = k.ce[0] * (by - By[im]) - k.ce[1] * (bx - Bx[jm]);
+    if (DIM == 3) {
+        const long long km = kz == 0 ? c + (g.n[2] - 1) * nxy : c - nxy;
+        cx -= k.ce[2] * (by - By[km]);                 // -d/dz B_y
+        cy += k.ce[2] * (bx - Bx[km]);                 // d/dz B_x
+    }
+    f.E[0][c] += cx - k.dt * f.J[0][c];
+    f.E[1][c] += cy - k.dt * f.J[1][c];
+    f.E[2][c] += cz - k.dt * f.J[2][c];
+    if (jclear.c[0]) {
+        static_cast<real*>(jclear.c[0])[c] = real(0);
+        static_cast<real*>(jclear.c[1])[c] = real(0);
+        static_cast<real*>(jclear.c[2])[c] = real(0);
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
+    return v;
+}
+
+// Sums NV values over the workgroup and adds them to acc[0 .. NV-1].
+template <int NV>
+__device__ inline void block_sum_add(double (&v)[NV], double* acc) {
+    __shared__ double part[kBlock / 64][NV];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) part[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w][threadIdx.x];
+        if (t != 0.0) atomicAdd(acc + threadIdx.x, t);
+    }
+}
+
+constexpr double kMeC2MeV = 0.51099895;   // electron rest energy
+
+template <typename real, int DIM>
+__device__ inline void reduce_one(int mode, const PArrays<real>& p, long long i, int sp,
+                                  const Geom& g, const ReduceArgs& ra, double (&v)[4],
+                                  double* rho) {
+    const double ux = p.u[0][i], uy = p.u[1][i], uz = p.u[2][i];
+    const double gamma = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    if (mode == RED_POLARIZATION) {
+        if (ra.species >= 0 && sp != ra.species) return;
+        const double ek = ra.mu[sp] * (gamma - 1.0) * kMeC2MeV;
+        if (ek >= ra.emin && ek < ra.emax) {
+            v[0] += (double)p.s[0][i];
+            v[1] += (double)p.s[1][i];
+            v[2] += (double)p.s[2][i];
+            v[3] += 1.0;
+        }
+    } else if (mode == RED_KINETIC) {
+        v[sp] += ra.mu[sp] * (gamma - 1.0) * (double)p.w[i];
+    } else {
+        int c[3];
+        unpack_cell<DIM>(p.cell[i], c[0], c[1], c[2]);
+        const double q = ra.Z[sp] * (double)p.w[i];
+        double o[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < DIM; ++a) o[a] = (double)p.off[a][i];
+        for (int corner = 0; corner < (1 << DIM); ++corner) {
+            double wgt = q;
+            int idx[3] = {0, 0, 0};
+            for (int a = 0; a < DIM; ++a) {
+                const int up = (corner >> a) & 1;
+                wgt *= up ? o[a] : 1.0 - o[a];
+                idx[a] = c[a] + up;
+                if (idx[a] >= g.n[a]) idx[a] -= g.n[a];
+            }
+            atomicAdd(rho + ((long long)idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0], wgt);
+        }
+    }
+}
+
+// Blocks [0, nseg) take one segment each; the remaining blocks stride over
+// the overflow store.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st,
+                   const int32_t* __restrict__ ctr, ReduceArgs ra, double* acc, double* rho,
+                   int nseg) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if ((int)blockIdx.x < nseg) {
+        const int sid = blockIdx.x;
+        const int sp = sid % g.nsp;
+        const long long start = seg.start[sid];
+        const int n = seg.count[sid];
+        for (int i = threadIdx.x; i < n; i += kBlock) reduce_one<real, DIM>(mode, p, start + i, sp, g, ra, v, rho);
+    } else {
+        const int n = ctr[CTR_STASH];
+        const int b = blockIdx.x - nseg, nb = gridDim.x - nseg;
+        for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock)
+            reduce_one<real, DIM>(mode, st, i, st.sp[i], g, ra, v, rho);
+    }
+    if (mode != RED_RHO) block_sum_add<4>(v, acc);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+k_field_energy(long long ncells, Fields<real> f, double* acc) {
+    double v[1] = {0.0};
+    for (long long c = blockIdx.x * (long long)kBlock + threadIdx.x; c < ncells;
+         c += (long long)gridDim.x * kBlock) {
+        double e = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double x = f.E[a][c], y = f.B[a][c];
+            e += x * x + y * y;
+        }
+        v[0] += 0.5 * e;
+    }
+    block_sum_add<1>(v, acc);
+}
+
+// div E at node (i, j, k) with backward differences, minus rho, in FP64.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_div_residual(Geom g, Vec3d inv_d, Fields<real> f, const double* rho, const double* ref,
+               double* ref_out, double* blockmax) {
+    const int nx = g.n[0], ny = g.n[1];
+    const long long nxy = (long long)nx * ny;
+    double m = 0.0;
+    for (long long c = blockIdx.x * (long long)kBlock + threadIdx.x; c < g.ncells;
+         c += (long long)gridDim.x * kBlock) {
+        const long long kz = c / nxy;
+        const long long rem = c - kz * nxy;
+        const int j = (int)(rem / nx);
+        const int i = (int)(rem - (long long)j * nx);
+        const long long im = i == 0 ? c + nx - 1 : c - 1;
+        const long long jm = j == 0 ? c + (long long)(ny - 1) * nx : c - nx;
+        double div = ((double)f.E[0][c] - (double)f.E[0][im]) * inv_d.v[0]
+                   + ((double)f.E[1][c] - (double)f.E[1][jm]) * inv_d.v[1];
+        if (DIM == 3) {
+            const long long km = kz == 0 ? c + (g.n[2] - 1) * nxy : c - nxy;
+            div += ((double)f.E[2][c] - (double)f.E[2][km]) * inv_d.v[2];
+        }
+        const double res = div - rho[c];
+        if (ref_out) ref_out[c] = res;
+        else m = fmax(m, fabs(res - ref[c]));
+    }
+    __shared__ double part[kBlock / 64];
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t = fmax(t, part[w]);
+        blockmax[blockIdx.x] = t;
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+k_nonfinite(const real* data, long long n, int32_t* flag) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        if (!isfinite(data[i])) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static dim3 field_grid(const Geom& g) {
+    return dim3((g.n[0] + kFx - 1) / kFx, (g.n[1] + kFy - 1) / kFy, g.ndim == 3 ? g.n[2] : 1);
+}
+
+template <typename real, int DIM>
+hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL((k_fdtd_b<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+                         real* const* jclear, hipStream_t stream) {
+    JClear jc{{nullptr, nullptr, nullptr}};
+    if (jclear)
+        for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
+    hipLaunchKernelGGL((k_fdtd_e<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f,
+                       jc);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>& p,
+                                   const Segs& seg, const PArrays<real>& st, const int32_t* ctr,
+                                   const ReduceArgs& ra, double* acc, double* rho,
+                                   hipStream_t stream) {
+    const int nseg = g.ntiles * g.nsp;
+    hipLaunchKernelGGL((k_reduce_particles<real, DIM>), dim3(nseg + 64), dim3(kBlock), 0, stream,
+                       mode, g, p, seg, st, ctr, ra, acc, rho, nseg);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_field_energy(const Geom& g, const Fields<real>& f, double* acc,
+                               hipStream_t stream) {
+    long long blocks = (g.ncells + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_field_energy<real>), dim3((unsigned)blocks), dim3(kBlock), 0, stream,
+                       g.ncells, f, acc);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_div_residual(const Geom& g, const Vec3d& inv_d, const Fields<real>& f,
+                               const double* rho, const double* ref, double* ref_out,
+                               double* blockmax, int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL((k_div_residual<real, DIM>), dim3(blocks), dim3(kBlock), 0, stream, g,
+                       inv_d, f, rho, ref, ref_out, blockmax);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStream_t stream) {
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_nonfinite<real>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, data,
+                       n, flag);
+    return hipGetLastError();
+}
+
+#define SPINPIC_INST_GRID(DIM)                                                                 \
+    template hipError_t launch_fdtd_b<double, DIM>(const Geom&, const Consts<double>&,        \
+                                                   const Fields<double>&, hipStream_t);        \
+    template hipError_t launch_fdtd_e<double, DIM>(const Geom&, const Consts<double>&,        \
+                                                   const Fields<double>&, double* const*,      \
+                                                   hipStream_t);                               \
+    template hipError_t launch_div_residual<double, DIM>(const Geom&, const Vec3d&,           \
+        const Fields<double>&, const double*, const double*, double*, double*, int, hipStream_t);
+
+#define SPINPIC_INST_PART(real, DIM)                                                           \
+    template hipError_t launch_reduce_particles<real, DIM>(int, const Geom&,                  \
+        const PArrays<real>&, const Segs&, const PArrays<real>&, const int32_t*,               \
+        const ReduceArgs&, double*, double*, hipStream_t);
+
+SPINPIC_INST_GRID(2)
+SPINPIC_INST_GRID(3)
+SPINPIC_INST_PART(float, 2)
+SPINPIC_INST_PART(float, 3)
+SPINPIC_INST_PART(double, 2)
+SPINPIC_INST_PART(double, 3)
+
+template hipError_t launch_field_energy<double>(const Geom&, const Fields<double>&, double*,
+                                                hipStream_t);
+template hipError_t launch_nonfinite<float>(const float*, long long, int32_t*, hipStream_t);
+template hipError_t launch_nonfinite<double>(const double*, long long, int32_t*, hipStream_t);
+
+}  // namespace spinpic

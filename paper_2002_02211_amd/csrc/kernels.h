@@ -1,0 +1,80 @@
+// Host-side launchers of the HIP kernels (internal to libspinpic).
+#pragma once
+
+#include "common.h"
+
+namespace spinpic {
+
+using freal = double;   // grid fields E, B, J
+
+template <typename real, typename acc_t>
+size_t tile_lds_bytes(const Geom& g);
+
+template <typename real, typename acc_t, int DIM>
+hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,
+                             const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
+                             const Fields<freal>& f, int deposit, hipStream_t stream);
+
+template <typename real, int DIM>
+hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
+                             const int32_t* ctr, const Fields<freal>& f, int deposit, int blocks,
+                             hipStream_t stream);
+
+template <typename real, int DIM>
+hipError_t launch_insert(const Geom& g, const PArrays<real>& p, const Segs& seg,
+                         const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
+                         unsigned long long* moved, int blocks, hipStream_t stream);
+
+template <typename real>
+hipError_t launch_repack_segments(const PArrays<real>& from, const PArrays<real>& to,
+                                  const int32_t* old_start, const int32_t* new_start,
+                                  const int32_t* count, int nseg, int ndim, hipStream_t stream);
+
+// Yee update: B -= (dt/2) curl E, or E += dt (curl B - J) while zeroing the
+// three current arrays jclear (may be NULL).
+template <typename real, int DIM>
+hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+                         hipStream_t stream);
+template <typename real, int DIM>
+hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+                         real* const* jclear, hipStream_t stream);
+
+// FP64 reductions.  acc receives sums by atomic adds and must be zeroed first.
+//   polarization: acc[0..2] += s, acc[3] += 1 over the selected particles.
+//   kinetic:      acc[sp] += mu (gamma - 1) w.
+//   rho:          rho (ncells doubles) += CIC charge Z w on the nodes.
+struct ReduceArgs {
+    int species;            // -1 = all
+    double emin, emax;      // MeV window [emin, emax)
+    double mu[kMaxSpecies];
+    double Z[kMaxSpecies];
+};
+
+template <typename real, int DIM>
+hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>& p,
+                                   const Segs& seg, const PArrays<real>& st, const int32_t* ctr,
+                                   const ReduceArgs& ra, double* acc, double* rho,
+                                   hipStream_t stream);
+enum { RED_POLARIZATION = 0, RED_KINETIC = 1, RED_RHO = 2 };
+
+// Field energy: acc[0] += sum (E^2 + B^2) / 2 over the cells.
+template <typename real>
+hipError_t launch_field_energy(const Geom& g, const Fields<real>& f, double* acc,
+                               hipStream_t stream);
+
+// div E - rho - ref at every node; per-block maxima of |.| into blockmax
+// (blocks entries), and, when ref_out is non-NULL, the value itself.
+struct Vec3d {
+    double v[3];
+};
+
+template <typename real, int DIM>
+hipError_t launch_div_residual(const Geom& g, const Vec3d& inv_d,
+                               const Fields<real>& f, const double* rho, const double* ref,
+                               double* ref_out, double* blockmax, int blocks, hipStream_t stream);
+
+// Non-finite probe over particle momenta/spins and fields: flag[0] = 1 if any.
+template <typename real>
+hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStream_t stream);
+
+}  // namespace spinpic

@@ -1,0 +1,537 @@
+// Particle kernels: fused gather + Boris + Thomas-BMT + move + Esirkepov
+// deposit per tile, the overflow-store push, and the per-step rebinning
+// (compaction of vacated slots and insertion of tile leavers).
+#include "common.h"
+#include "kernels.h"
+
+namespace spinpic {
+
+// Current sink into the shared-memory J tile.  Node l of the tile (local
+// index, -1 .. T+1) is shared-memory coordinate l + 1.
+template <typename acc_t, int DIM>
+struct TileJ {
+    acc_t* base;
+    int Hx, Hxy, H;
+    int o;   // offset of the stencil's base node
+    template <typename real>
+    __device__ inline void operator()(int c, int i, int j, int k, real v) const {
+        if (v != real(0))
+            atomicAdd(base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i, (acc_t)v);
+    }
+};
+
+// Current sink straight into global J with periodic wrap.
+template <typename freal, int DIM>
+struct GlobalJ {
+    freal* J[3];
+    int n[3];
+    int b[3];  // absolute base node
+    template <typename real>
+    __device__ inline void operator()(int c, int i, int j, int k, real v) const {
+        if (v == real(0)) return;
+        const int ix = wrap_index(b[0] + i, n[0]);
+        const int iy = wrap_index(b[1] + j, n[1]);
+        const int iz = DIM == 3 ? wrap_index(b[2] + k, n[2]) : 0;
+        atomicAdd(J[c] + ((long long)iz * n[1] + iy) * n[0] + ix, (freal)v);
+    }
+};
+
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+template <typename real, typename acc_t>
+size_t tile_lds_bytes(const Geom& g) {
+    const int Gz = g.ndim == 3 ? g.T[2] + 2 : 1;
+    const int Hz = g.ndim == 3 ? g.T[2] + 3 : 1;
+    const size_t G = (size_t)(g.T[0] + 2) * (g.T[1] + 2) * Gz;
+    const size_t H = (size_t)(g.T[0] + 3) * (g.T[1] + 3) * Hz;
+    return align16(6 * G * sizeof(real)) + 3 * H * sizeof(acc_t);
+}
+
+// Wrap an index that is at most a few periods outside [0, n).
+__device__ inline int wrap_near(int i, int n) {
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
+
+// Exclusive prefix count of pred over the workgroup; *total gets the sum.
+// Every thread of the workgroup must call it.
+__device__ inline int block_exclusive_count(bool pred, int* total) {
+    __shared__ int wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(pred);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        before += w < wv ? wsum[w] : 0;
+        sum += wsum[w];
+    }
+    __syncthreads();
+    *total = sum;
+    return before + rank;
+}
+
+template <typename real>
+__device__ inline void copy_particle(const PArrays<real>& from, long long i, const PArrays<real>& to,
+                                     long long j, int ndim) {
+    to.cell[j] = from.cell[i];
+    for (int a = 0; a < ndim; ++a) to.off[a][j] = from.off[a][i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        to.u[a][j] = from.u[a][i];
+        to.s[a][j] = from.s[a][i];
+    }
+    to.w[j] = from.w[i];
+    to.id[j] = from.id[i];
+}
+
+// Close the holes a segment's leavers left: with L leavers out of n the
+// segment shrinks to n - L slots, and the particles still present in the
+// tail [n - L, n) move into the holes below n - L.  Runs in the workgroup
+// that just pushed the segment; its stores are visible to it after the
+// barrier.  Every thread must call it.
+template <typename real>
+__device__ void compact_segment(const PArrays<real>& p, const Segs& seg, int start, int n, int L,
+                                int ndim) {
+    const int nn = n - L;
+    for (int t = threadIdx.x; t < L; t += kBlock) {
+        const int h = seg.holes[start + t];
+        if (h >= nn) seg.slotflag[start + h] = 1;
+    }
+    __syncthreads();
+    int done = 0, total = 0;
+    for (int b = 0; b < L; b += kBlock) {
+        const int j = b + threadIdx.x;
+        const bool src = j < L && seg.slotflag[start + nn + j] == 0;
+        const int rank = block_exclusive_count(src, &total);
+        if (src) seg.srclist[start + done + rank] = nn + j;
+        done += total;
+    }
+    __syncthreads();
+    done = 0;
+    for (int b = 0; b < L; b += kBlock) {
+        const int t = b + threadIdx.x;
+        const int h = t < L ? seg.holes[start + t] : n;
+        const bool front = h < nn;
+        const int rank = block_exclusive_count(front, &total);
+        if (front) {
+            const int from = seg.srclist[start + done + rank];
+            copy_particle(p, (long long)start + from, p, (long long)start + h, ndim);
+        }
+        done += total;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < L; t += kBlock) {
+        const int h = seg.holes[start + t];
+        if (h >= nn) seg.slotflag[start + h] = 0;
+    }
+}
+
+// One workgroup per tile.  The tile's E and B, with one guard cell on each
+// side, are staged in shared memory (rounded to the push precision); every
+// particle of every species in the tile gathers from there, is pushed and
+// moved, and deposits its Esirkepov current into a shared-memory J tile
+// (tile + 1 guard node below, 2 above), which is added to global J once at
+// the end.  Particles that stay in the tile are written back in place; those
+// that leave are appended to the leaver store, and the tile closes the holes
+// they leave before it finishes.
+template <typename real, typename acc_t, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
+             int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_nleave;
+
+    // the other step's leaver counter is free again: clear it for the next step
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
+
+    // consecutive tiles go to the same XCD (workgroups are dealt round-robin
+    // over the 8 XCDs), so neighbours share guard cells in one L2
+    const int per = (g.ntiles + 7) >> 3;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= g.ntiles) return;
+    int tc[3];
+    tc[0] = t % g.nt[0];
+    tc[1] = (t / g.nt[0]) % g.nt[1];
+    tc[2] = t / (g.nt[0] * g.nt[1]);
+    int org[3], ext[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        org[a] = tc[a] * g.T[a];
+        ext[a] = min(g.T[a], g.n[a] - org[a]);
+    }
+
+    const int Gx = g.T[0] + 2, Gy = g.T[1] + 2, Gz = DIM == 3 ? g.T[2] + 2 : 1;
+    const int Gxy = Gx * Gy, G = Gxy * Gz;
+    const int Hx = g.T[0] + 3, Hy = g.T[1] + 3, Hz = DIM == 3 ? g.T[2] + 3 : 1;
+    const int Hxy = Hx * Hy, H = Hxy * Hz;
+    real* F = reinterpret_cast<real*>(smem);
+    acc_t* Jl = reinterpret_cast<acc_t*>(smem + align16((size_t)6 * G * sizeof(real)));
+
+    // stage E and B: each thread owns one x position of several rows
+    {
+        const int rpp = kBlock / Gx;              // rows per pass
+        const int r0 = threadIdx.x / Gx;
+        const int gx = threadIdx.x - r0 * Gx;
+        const long long ix = wrap_near(org[0] - 1 + gx, g.n[0]);
+        if (r0 < rpp) {
+            for (int gz = 0; gz < Gz; ++gz) {
+                const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + gz, g.n[2]) : 0;
+                for (int gy = r0; gy < Gy; gy += rpp) {
+                    const long long iy = wrap_near(org[1] - 1 + gy, g.n[1]);
+                    const long long gi = (iz * g.n[1] + iy) * g.n[0] + ix;
+                    const int li = gz * Gxy + gy * Gx + gx;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c * G + li] = (real)f.E[c][gi];
+                        F[(3 + c) * G + li] = (real)f.B[c][gi];
+                    }
+                }
+            }
+        }
+    }
+    if (deposit)
+        for (int idx = threadIdx.x; idx < 3 * H; idx += kBlock) Jl[idx] = acc_t(0);
+    __syncthreads();
+
+    const TileFields<real, DIM> TF{F, Gx, Gxy, G};
+    const int lane = threadIdx.x & 63;
+    const real half_dt = real(0.5) * k.dt;
+
+    for (int sp = 0; sp < g.nsp; ++sp) {
+        const int sid = t * g.nsp + sp;
+        const int start = seg.start[sid];
+        const int n = seg.count[sid];
+        if (threadIdx.x == 0) s_nleave = 0;
+        __syncthreads();
+        const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
+
+        for (int base = 0; base < n; base += kBlock) {
+            const int i = base + threadIdx.x;
+            const bool active = i < n;
+            const long long pi = (long long)start + i;
+            bool leave = false;
+            int newcell = 0;
+            real o[3] = {real(0), real(0), real(0)}, u[3], s[3], wgt = real(0);
+            if (active) {
+                int c[3];
+                unpack_cell<DIM>(p.cell[pi], c[0], c[1], c[2]);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) o[a] = p.off[a][pi];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = p.u[a][pi];
+                    s[a] = p.s[a][pi];
+                }
+                wgt = p.w[pi];
+
+                int l[3] = {c[0] - org[0], c[1] - org[1], DIM == 3 ? c[2] - org[2] : 0};
+                Stencil1<real> st[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    st[a] = a < DIM ? stencil1(l[a], o[a]) : Stencil1<real>{0, real(0), 0, real(0)};
+                real E[3], B[3];
+                gather_all(TF, st, E, B);
+                boris_tbmt(u, s, E, B, eps, r, an, half_dt);
+
+                const real ig = rsqrt1(real(1) + dot3(u, u));
+                real o0[3];
+                int dc[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    o0[a] = o[a];
+                    dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+                }
+                if (deposit) {
+                    real S0[3][3], S1[3][3], q[3];
+                    int b[3] = {0, 0, 0};
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        b[a] = l[a] + shape_pair(o0[a], o[a], dc[a], S0[a], S1[a]);
+                        q[a] = -Z * wgt * k.d_dt[a];
+                    }
+                    TileJ<acc_t, DIM> sink{Jl, Hx, Hxy, H,
+                                           (DIM == 3 ? (b[2] + 1) * Hxy : 0) + (b[1] + 1) * Hx + (b[0] + 1)};
+                    esirkepov<real, DIM>(S0, S1, q, Z * wgt * u[2] * ig, sink);
+                }
+                int nc[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    nc[a] = c[a];
+                    if (a < DIM) {
+                        const int nl = l[a] + dc[a];
+                        // along an axis with one tile the wrap comes back in
+                        leave = leave || (g.nt[a] > 1 && (nl < 0 || nl >= ext[a]));
+                        nc[a] = c[a] + dc[a];
+                        if (nc[a] < 0) nc[a] += g.n[a];
+                        if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
+                    }
+                }
+                newcell = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+            }
+
+            const unsigned long long m = __ballot(leave);
+            if (m) {
+                const int cnt = __popcll(m);
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                int lbase = 0, hbase = 0;
+                if (lane == leader) {
+                    lbase = atomicAdd(&ctr[slot], cnt);
+                    hbase = atomicAdd(&s_nleave, cnt);
+                }
+                lbase = __shfl(lbase, leader);
+                hbase = __shfl(hbase, leader);
+                if (leave) {
+                    const int L = lbase + rank;
+                    lv.cell[L] = newcell;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) lv.off[a][L] = o[a];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        lv.u[a][L] = u[a];
+                        lv.s[a][L] = s[a];
+                    }
+                    lv.w[L] = wgt;
+                    lv.id[L] = p.id[pi];
+                    lv.sp[L] = sp;
+                    seg.holes[start + hbase + rank] = i;
+                }
+            }
+            if (active && !leave) {
+                p.cell[pi] = newcell;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) p.off[a][pi] = o[a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    p.u[a][pi] = u[a];
+                    p.s[a][pi] = s[a];
+                }
+            }
+        }
+        __syncthreads();
+        const int L = s_nleave;
+        if (L > 0) compact_segment(p, seg, start, n, L, DIM);
+        if (threadIdx.x == 0) seg.count[sid] = n - L;
+        __syncthreads();
+    }
+
+    if (deposit) {
+        __syncthreads();
+        const int rpp = kBlock / Hx;
+        const int r0 = threadIdx.x / Hx;
+        const int hx = threadIdx.x - r0 * Hx;
+        const long long ix = wrap_near(org[0] - 1 + hx, g.n[0]);
+        if (r0 < rpp) {
+            for (int hz = 0; hz < Hz; ++hz) {
+                const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + hz, g.n[2]) : 0;
+                for (int hy = r0; hy < Hy; hy += rpp) {
+                    const long long iy = wrap_near(org[1] - 1 + hy, g.n[1]);
+                    const long long gi = (iz * g.n[1] + iy) * g.n[0] + ix;
+                    const int li = hz * Hxy + hy * Hx + hx;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const acc_t v = Jl[c * H + li];
+                        if (v != acc_t(0)) atomicAdd(f.J[c] + gi, (freal)v);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Particles in the overflow store (tiles that ran out of slots): the same
+// step, gathering from and depositing into global memory directly.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict__ ctr,
+             Fields<freal> f, int deposit) {
+    const int n = ctr[CTR_STASH];
+    GlobalFields<freal, DIM> GF;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        GF.c[c] = f.E[c];
+        GF.c[3 + c] = f.B[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) GF.n[a] = g.n[a];
+    const real half_dt = real(0.5) * k.dt;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int sp = st.sp[i];
+        int c[3];
+        unpack_cell<DIM>(st.cell[i], c[0], c[1], c[2]);
+        real o[3] = {real(0), real(0), real(0)}, u[3], s[3];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) o[a] = st.off[a][i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[a] = st.u[a][i];
+            s[a] = st.s[a][i];
+        }
+        const real wgt = st.w[i];
+        Stencil1<real> stc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            stc[a] = a < DIM ? stencil1(c[a], o[a]) : Stencil1<real>{0, real(0), 0, real(0)};
+        real E[3], B[3];
+        gather_all(GF, stc, E, B);
+        boris_tbmt(u, s, E, B, k.eps[sp], k.r[sp], k.a[sp], half_dt);
+        const real ig = real(1) / fsqrt(real(1) + dot3(u, u));
+        real o0[3];
+        int dc[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            o0[a] = o[a];
+            dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+        }
+        if (deposit) {
+            real S0[3][3], S1[3][3], q[3];
+            GlobalJ<freal, DIM> sink;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sink.J[a] = f.J[a];
+                sink.n[a] = g.n[a];
+                sink.b[a] = 0;
+            }
+            const real Z = k.Z[sp];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                sink.b[a] = c[a] + shape_pair(o0[a], o[a], dc[a], S0[a], S1[a]);
+                q[a] = -Z * wgt * k.d_dt[a];
+            }
+            esirkepov<real, DIM>(S0, S1, q, Z * wgt * u[2] * ig, sink);
+        }
+        int nc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            nc[a] = c[a] + dc[a];
+            if (a < DIM) {
+                if (nc[a] < 0) nc[a] += g.n[a];
+                if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
+            }
+        }
+        st.cell[i] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) st.off[a][i] = o[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            st.u[a][i] = u[a];
+            st.s[a][i] = s[a];
+        }
+    }
+}
+
+// Every leaver takes a slot at the end of its new segment, or a slot in the
+// overflow store when the segment is full.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_insert(Geom g, PArrays<real> p, Segs seg, PArrays<real> lv, PArrays<real> st,
+         int32_t* __restrict__ ctr, int slot, unsigned long long* __restrict__ moved) {
+    const int L = ctr[slot];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(moved, (unsigned long long)L);
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < L; q += gridDim.x * kBlock) {
+        int c[3];
+        unpack_cell<DIM>(lv.cell[q], c[0], c[1], c[2]);
+        const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1] + (DIM == 3 ? g.nt[1] * (c[2] / g.T[2]) : 0));
+        const int sp = lv.sp[q];
+        const int sid = tile * g.nsp + sp;
+        const int pos = atomicAdd(&seg.count[sid], 1);
+        if (pos < seg.cap[sid]) {
+            copy_particle(lv, q, p, (long long)seg.start[sid] + pos, DIM);
+        } else {
+            atomicSub(&seg.count[sid], 1);
+            const int j = atomicAdd(&ctr[CTR_STASH], 1);
+            copy_particle(lv, q, st, j, DIM);
+            st.sp[j] = sp;
+        }
+    }
+}
+
+// Re-layout after a capacity change: segment sid moves from old_start to
+// new_start (one workgroup per segment).
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+k_repack_segments(PArrays<real> from, PArrays<real> to, const int32_t* __restrict__ old_start,
+                  const int32_t* __restrict__ new_start, const int32_t* __restrict__ count,
+                  int ndim) {
+    const int sid = blockIdx.x;
+    const long long a = old_start[sid], b = new_start[sid];
+    const int n = count[sid];
+    for (int i = threadIdx.x; i < n; i += kBlock) copy_particle(from, a + i, to, b + i, ndim);
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename real>
+hipError_t launch_repack_segments(const PArrays<real>& from, const PArrays<real>& to,
+                                  const int32_t* old_start, const int32_t* new_start,
+                                  const int32_t* count, int nseg, int ndim, hipStream_t stream) {
+    hipLaunchKernelGGL((k_repack_segments<real>), dim3(nseg), dim3(kBlock), 0, stream, from, to,
+                       old_start, new_start, count, ndim);
+    return hipGetLastError();
+}
+
+template <typename real, typename acc_t, int DIM>
+hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,
+                             const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
+                             const Fields<freal>& f, int deposit, hipStream_t stream) {
+    const size_t lds = tile_lds_bytes<real, acc_t>(g);
+    const int grid = ((g.ntiles + 7) >> 3) * 8;
+    hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM>), dim3(grid), dim3(kBlock), lds, stream,
+                       g, k, p, seg, lv, ctr, slot, f, deposit);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
+                             const int32_t* ctr, const Fields<freal>& f, int deposit,
+                             int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL((k_push_stash<real, DIM>), dim3(blocks), dim3(kBlock), 0, stream,
+                       g, k, st, ctr, f, deposit);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_insert(const Geom& g, const PArrays<real>& p, const Segs& seg,
+                         const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
+                         unsigned long long* moved, int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL((k_insert<real, DIM>), dim3(blocks), dim3(kBlock), 0, stream,
+                       g, p, seg, lv, st, ctr, slot, moved);
+    return hipGetLastError();
+}
+
+#define SPINPIC_INST_PUSH(real, acc, DIM)                                                       \
+    template hipError_t launch_push_tiles<real, acc, DIM>(const Geom&, const Consts<real>&,    \
+        const PArrays<real>&, const Segs&, const PArrays<real>&, int32_t*, int,                \
+        const Fields<freal>&, int, hipStream_t);
+
+SPINPIC_INST_PUSH(float, float, 2)
+SPINPIC_INST_PUSH(float, float, 3)
+SPINPIC_INST_PUSH(float, double, 2)
+SPINPIC_INST_PUSH(float, double, 3)
+SPINPIC_INST_PUSH(double, double, 2)
+SPINPIC_INST_PUSH(double, double, 3)
+template size_t tile_lds_bytes<float, float>(const Geom&);
+template size_t tile_lds_bytes<float, double>(const Geom&);
+template size_t tile_lds_bytes<double, double>(const Geom&);
+
+#define SPINPIC_INST_REST(real, DIM)                                                            \
+    template hipError_t launch_push_stash<real, DIM>(const Geom&, const Consts<real>&,         \
+        const PArrays<real>&, const int32_t*, const Fields<freal>&, int, int, hipStream_t);    \
+    template hipError_t launch_insert<real, DIM>(const Geom&, const PArrays<real>&,            \
+        const Segs&, const PArrays<real>&, const PArrays<real>&, int32_t*, int,                 \
+        unsigned long long*, int, hipStream_t);
+
+SPINPIC_INST_REST(float, 2)
+SPINPIC_INST_REST(float, 3)
+SPINPIC_INST_REST(double, 2)
+SPINPIC_INST_REST(double, 3)
+
+template hipError_t launch_repack_segments<float>(const PArrays<float>&, const PArrays<float>&,
+    const int32_t*, const int32_t*, const int32_t*, int, int, hipStream_t);
+template hipError_t launch_repack_segments<double>(const PArrays<double>&, const PArrays<double>&,
+    const int32_t*, const int32_t*, const int32_t*, int, int, hipStream_t);
+}  // namespace spinpic

@@ -1,0 +1,334 @@
+"""ctypes binding of libspinpic (include/spinpic.h).
+
+The functions ``pic_init``, ``pic_step``, ``pic_polarization``, ``pic_fields``,
+``pic_particles``, ``pic_energy``, ``pic_stats``, ``pic_timing``,
+``pic_timing_read`` and ``pic_free`` mirror the C calls one to one: they only
+marshal arguments (numpy arrays in, numpy arrays out) and raise ``PicError``
+on a negative status.  Every step of the computation runs in the HIP kernels
+of the library; there is no fallback path.  Device memory comes from torch's
+caching allocator and work is enqueued on torch's current stream.
+"""
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspinpic.so")
+
+PIC_OK, PIC_EINVAL, PIC_ECFL, PIC_EHIP, PIC_ECAPACITY, PIC_ENONFINITE, PIC_ESTATE, PIC_ENOMEM = \
+    0, -1, -2, -3, -4, -5, -6, -7
+PIC_FP64, PIC_FP32_MIXED = 0, 1
+PIC_ACC_DEFAULT, PIC_ACC_FP32, PIC_ACC_FP64 = 0, 1, 2
+PIC_FLAG_TEST_PARTICLE = 1
+MAX_SPECIES = 4
+FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
+EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
+            "pic_energy", "pic_stats", "pic_timing", "pic_timing_read", "pic_last_error",
+            "pic_free")
+
+_ERR_NAMES = {PIC_EINVAL: "PIC_EINVAL", PIC_ECFL: "PIC_ECFL", PIC_EHIP: "PIC_EHIP",
+              PIC_ECAPACITY: "PIC_ECAPACITY", PIC_ENONFINITE: "PIC_ENONFINITE",
+              PIC_ESTATE: "PIC_ESTATE", PIC_ENOMEM: "PIC_ENOMEM"}
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERR_NAMES.get(code, "?"), code, msg))
+        self.code = code
+        self.msg = msg
+
+
+class Species(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_double), ("mu", ctypes.c_double), ("a", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("d", ctypes.c_double * 3),
+        ("dt", ctypes.c_double), ("precision", ctypes.c_int32), ("nspecies", ctypes.c_int32),
+        ("sp", Species * MAX_SPECIES), ("tile", ctypes.c_int32 * 3), ("slack", ctypes.c_double),
+        ("flags", ctypes.c_int32), ("deposit_acc", ctypes.c_int32),
+    ]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64 * MAX_SPECIES),
+                ("particles", ctypes.c_void_p * MAX_SPECIES),
+                ("fields", ctypes.c_void_p)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libspinpic.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libspinpic.so is not built (%s); run "
+                           "`python -m paper_2002_02211_amd.build`" % path)
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes the library bind to that one, so the streams and device pointers
+    # torch hands over belong to the runtime the library calls
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.pic_init.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(State),
+                             ctypes.POINTER(Allocator), P, ctypes.POINTER(P)]
+    lib.pic_step.argtypes = [P, ctypes.c_int32]
+    lib.pic_polarization.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_fields.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]
+    lib.pic_particles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_energy.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    lib.pic_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.pic_timing.argtypes = [P, ctypes.c_int32]
+    lib.pic_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.pic_last_error.argtypes = [P]
+    lib.pic_last_error.restype = ctypes.c_char_p
+    lib.pic_free.argtypes = [P]
+    lib.pic_free.restype = None
+    for name in EXPORTED:
+        if name not in ("pic_last_error", "pic_free"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code, ctx=None):
+    if code != PIC_OK:
+        lib = load_library()
+        msg = lib.pic_last_error(ctx)
+        raise PicError(code, msg.decode() if msg else "")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------- config
+
+def make_config(ndim, n, d, dt, species, precision=PIC_FP64, tile=(0, 0, 0), slack=0.0,
+                flags=0, deposit_acc=PIC_ACC_DEFAULT):
+    cfg = Config()
+    cfg.ndim = int(ndim)
+    for a in range(3):
+        cfg.n[a] = int(n[a]) if a < len(n) else 1
+        cfg.d[a] = float(d[a]) if a < len(d) else 1.0
+        cfg.tile[a] = int(tile[a]) if a < len(tile) else 0
+    cfg.dt = float(dt)
+    cfg.precision = int(precision)
+    cfg.nspecies = len(species)
+    for s, sp in enumerate(species[:MAX_SPECIES]):
+        cfg.sp[s].Z = float(sp["Z"])
+        cfg.sp[s].mu = float(sp["mu"])
+        cfg.sp[s].a = float(sp["a"])
+    cfg.slack = float(slack)
+    cfg.flags = int(flags)
+    cfg.deposit_acc = int(deposit_acc)
+    return cfg
+
+
+def config_from_spec(spec, precision=None, tile=None, test_particle=False, slack=0.0,
+                     deposit_acc=PIC_ACC_DEFAULT):
+    """Config from a workload recipe dict (ndim, n, d, dt, species, ...)."""
+    if precision is None:
+        precision = spec.get("precision", "fp64")
+    if isinstance(precision, str):
+        precision = {"fp64": PIC_FP64, "fp32": PIC_FP32_MIXED}[precision]
+    if tile is None:
+        tile = spec.get("tile", (0, 0, 0))
+        if spec["ndim"] == 3 and precision == PIC_FP64:
+            tile = (0, 0, 0)
+    return make_config(spec["ndim"], spec["n"], spec["d"], spec["dt"], spec["species"],
+                       precision=precision, tile=tile, slack=slack,
+                       flags=PIC_FLAG_TEST_PARTICLE if test_particle else 0,
+                       deposit_acc=deposit_acc)
+
+
+# ---------------------------------------------------------------- torch glue
+
+class _TorchMemory:
+    """Device allocator and stream backed by torch's caching allocator."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+
+        def _alloc(user, size):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(size), self.device, self.stream)
+            except Exception:   # noqa: BLE001 - reported to C as NULL
+                return None
+
+        def _free(user, ptr):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_fn = ALLOC_FN(_alloc)
+        self._free_fn = FREE_FN(_free)
+        self.allocator = Allocator(self._alloc_fn, self._free_fn, None)
+
+    @property
+    def stream_handle(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C calls
+
+def pic_init(cfg, particles, fields=None, device=0, memory=None):
+    """Create a context.  particles: list of (N, 10) float64 arrays per species
+    (x y z ux uy uz sx sy sz w); fields: (6, nz, ny, nx) float64 or None.
+    Returns (ctx, memory) - keep ``memory`` alive as long as the context."""
+    lib = load_library()
+    st = State()
+    keep = []
+    for s in range(MAX_SPECIES):
+        if s < len(particles) and particles[s] is not None and len(particles[s]):
+            arr = np.ascontiguousarray(particles[s], dtype=np.float64)
+            if arr.ndim != 2 or arr.shape[1] != 10:
+                raise ValueError("particles[%d] must have shape (N, 10)" % s)
+            keep.append(arr)
+            st.count[s] = arr.shape[0]
+            st.particles[s] = arr.ctypes.data
+        else:
+            st.count[s] = 0
+            st.particles[s] = None
+    if fields is not None:
+        F = np.ascontiguousarray(fields, dtype=np.float64)
+        keep.append(F)
+        st.fields = F.ctypes.data
+    if memory is None:
+        memory = _TorchMemory(device)
+    ctx = ctypes.c_void_p()
+    code = lib.pic_init(ctypes.byref(cfg), ctypes.byref(st), ctypes.byref(memory.allocator),
+                        memory.stream_handle, ctypes.byref(ctx))
+    _check(code, None)
+    return ctx, memory
+
+
+def pic_step(ctx, nsteps=1):
+    _check(load_library().pic_step(ctx, int(nsteps)), ctx)
+
+
+def pic_polarization(ctx, species=-1, ekin_min_mev=-math.inf, ekin_max_mev=math.inf):
+    P = np.zeros(3)
+    N = ctypes.c_int64()
+    _check(load_library().pic_polarization(ctx, int(species), float(ekin_min_mev),
+                                           float(ekin_max_mev), _dptr(P), ctypes.byref(N)), ctx)
+    return P, int(N.value)
+
+
+def pic_fields(ctx, mask, cells):
+    ncomp = bin(int(mask)).count("1")
+    out = np.empty(ncomp * cells)
+    _check(load_library().pic_fields(ctx, int(mask), _dptr(out), out.size), ctx)
+    return out
+
+
+def pic_particles(ctx, species, count):
+    out = np.empty((count, 11))
+    n = ctypes.c_int64()
+    _check(load_library().pic_particles(ctx, int(species), _dptr(out), out.size, ctypes.byref(n)), ctx)
+    return out[: n.value]
+
+
+def pic_energy(ctx, nspecies):
+    out = np.empty(nspecies + 2)
+    _check(load_library().pic_energy(ctx, _dptr(out), out.size), ctx)
+    return out
+
+
+def pic_stats(ctx):
+    out = (ctypes.c_int64 * 5)()
+    _check(load_library().pic_stats(ctx, out, 5), ctx)
+    return {"steps": out[0], "moved": out[1], "overflow": out[2], "repacks": out[3],
+            "particles": out[4]}
+
+
+def pic_timing(ctx, enable):
+    _check(load_library().pic_timing(ctx, int(bool(enable))), ctx)
+
+
+TIMER_NAMES = ("push_deposit", "overflow_push", "insert", "fdtd")
+
+
+def pic_timing_read(ctx):
+    ms = np.zeros(len(TIMER_NAMES))
+    n = (ctypes.c_int64 * len(TIMER_NAMES))()
+    _check(load_library().pic_timing_read(ctx, _dptr(ms), n, len(TIMER_NAMES)), ctx)
+    return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(TIMER_NAMES)}
+
+
+def pic_free(ctx):
+    load_library().pic_free(ctx)
+
+
+# ---------------------------------------------------------------- convenience
+
+class Simulation:
+    """A context plus its shapes: the calls above as methods."""
+
+    def __init__(self, cfg, particles, fields=None, device=0):
+        self.cfg = cfg
+        self.nspecies = cfg.nspecies
+        self.shape = (cfg.n[2] if cfg.ndim == 3 else 1, cfg.n[1], cfg.n[0])
+        self.cells = int(np.prod(self.shape))
+        self.counts = [len(p) if p is not None else 0 for p in particles]
+        self.ctx, self._mem = pic_init(cfg, particles, fields, device=device)
+
+    def step(self, n=1):
+        pic_step(self.ctx, n)
+
+    def polarization(self, species=-1, emin=-math.inf, emax=math.inf):
+        return pic_polarization(self.ctx, species, emin, emax)
+
+    def fields(self, names=FIELD_NAMES):
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES.index(nm)
+        out = pic_fields(self.ctx, mask, self.cells)
+        order = [nm for nm in FIELD_NAMES if nm in names]
+        arr = out.reshape((len(order),) + self.shape)
+        return {nm: arr[i] for i, nm in enumerate(order)}
+
+    def particles(self, species):
+        return pic_particles(self.ctx, species, self.counts[species])
+
+    def energy(self):
+        return pic_energy(self.ctx, self.nspecies)
+
+    def stats(self):
+        return pic_stats(self.ctx)
+
+    def timing(self, enable=True):
+        pic_timing(self.ctx, enable)
+
+    def timing_read(self):
+        return pic_timing_read(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            pic_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass

@@ -146,3 +146,20 @@ def test_laser_peak_and_polarization():
     amp = np.sqrt(F3[1] ** 2 + F3[2] ** 2)
     assert np.max(amp) <= 3.0 + 1e-12
     assert np.max(np.abs(F3[4])) > 0.5
+
+
+def test_store_fp32_rounds_the_stored_state_only():
+    """With store_fp32 the stored offsets, momenta and spins are float32 values
+    after every step; with it off, the same run keeps float64 values."""
+    spec = synth.preset("small2d", n=(24, 16, 1))
+    state = synth.make_state(spec)
+    a = oracle.Sim(spec, state, store_fp32=True)
+    b = oracle.Sim(spec, state)
+    a.step(2)
+    b.step(2)
+    for k in range(2):
+        for arr in (a.u[k], a.s[k], a.w[k], a.xi[k][:, :2] - np.floor(a.xi[k][:, :2])):
+            np.testing.assert_array_equal(arr, arr.astype(np.float32).astype(np.float64))
+        assert np.any(b.u[k] != b.u[k].astype(np.float32).astype(np.float64))
+        # the rounding is a perturbation at float32 resolution, not a change of method
+        assert np.max(np.abs(a.u[k] - b.u[k])) < 1e-5
