@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--precision", default=None, choices=("fp32", "fp64"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
+                    help="precision of the per-tile shared-memory current sums (FP32 path)")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000,
                     help="particles per species in the CPU-baseline sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -139,7 +141,8 @@ def main():
         del a, b
 
     t0 = time.time()
-    cfg = S.config_from_spec(spec, precision=precision)
+    acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
+    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc)
     sim = S.Simulation(cfg, state["particles"], state["fields"])
     torch.cuda.synchronize()
     print("[bench] init (sort + upload) %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)

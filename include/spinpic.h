@@ -93,7 +93,8 @@ typedef struct {
     int32_t flags;       /* PIC_FLAG_* */
     int32_t deposit_acc; /* PIC_FP32_MIXED only: precision of the per-tile
                             shared-memory current sums that precede the one FP64
-                            global add per node (PIC_ACC_*; default FP64) */
+                            global add per node (PIC_ACC_*; PIC_ACC_DEFAULT is
+                            FP64) */
 } pic_config;
 
 /* Initial state, all host memory in float64, copied during pic_init. */

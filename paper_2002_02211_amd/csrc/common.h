@@ -103,6 +103,19 @@ __host__ __device__ inline int wrap_index(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+// Element access through a uniform base pointer and a 32-bit byte offset:
+// the compiler folds this into scalar-base + vector-offset loads and stores
+// (one offset register shared by every array) instead of a 64-bit address
+// per lane and array.  Slot counts are bounded so offsets fit in 32 bits.
+template <typename T>
+__device__ inline T ldo(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ inline void sto(T* base, uint32_t byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // ---------------------------------------------------------------- math
 
 __device__ inline float fsqrt(float x) { return sqrtf(x); }
@@ -356,81 +369,108 @@ __device__ inline int shape_pair(real o0, real o1, int dc, real S0[3], real S1[3
 }
 
 // Esirkepov current of one particle.  sink(c, i, j, k, v) adds v to J_c at
-// stencil node (i, j, k) relative to the base node b.  With q_a = -Z w d_a/dt,
-// J_a at b + i + 1/2 along a is q_a times the running sum of W_a over the
-// nodes up to i, so that (rho^(n+1) - rho^n)/dt + div J = 0 on every node.
-//   2D: W_x = DSx (S0y + DSy/2), W_y = (S0x + DSx/2) DSy,
-//       J_z = Z w v_z [S0x S0y + (DSx S0y + S0x DSy)/2 + DSx DSy/3].
+// stencil node (i, j, k) relative to the base node b (the lower of the old
+// and new cell along each axis).  With q_a = -Z w d_a/dt, J_a at b + i + 1/2
+// along a is q_a times the running sum of W_a over the nodes up to i, so that
+// (rho^(n+1) - rho^n)/dt + div J = 0 on every node.  With DS = S1 - S0:
+//   2D: W_x = DSx (S0y + DSy/2), W_y = (S0x + DSx/2) DSy, and
+//       J_z = Z w v_z [S0x S0y + (DSx S0y + S0x DSy)/2 + DSx DSy/3];
 //   3D: W_x = DSx (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3), cyclic.
+// The running sum up to node 1 is written as -W at node 2 (the sum over all
+// three nodes vanishes), so that along an axis the particle does not cross
+// every entry on node 2 is exactly zero.  The eight (2D) or twelve (3D)
+// entries that can be nonzero without a crossing are added for every lane;
+// the others only by lanes that changed cell.
 template <typename real, int DIM, class Sink>
-__device__ inline void esirkepov(const real S0[3][3], const real S1[3][3],
+__device__ inline void esirkepov(const real S0[3][3], const real S1[3][3], const int dc[3],
                                  const real q[3], real qz2d, Sink& sink) {
-    real DS[3][3];
+    real DS[3][3], h[3][3], gq[3][3], C[3][2];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) DS[a][k] = S1[a][k] - S0[a][k];
-    if (DIM == 2) {
-        // J_x at (b+i+1/2, b+j): -qx * sum_{i'<=i} DSx[i'] (S0y[j] + DSy[j]/2)
-        real hy[3], hx[3];
+    for (int a = 0; a < DIM; ++a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            hy[k] = S0[1][k] + real(0.5) * DS[1][k];
-            hx[k] = S0[0][k] + real(0.5) * DS[0][k];
+            DS[a][k] = S1[a][k] - S0[a][k];
+            h[a][k] = S0[a][k] + real(0.5) * DS[a][k];               // S0 + DS/2
+            gq[a][k] = real(0.5) * S0[a][k] + (real(1) / real(3)) * DS[a][k];  // S0/2 + DS/3
         }
-        const real cx0 = DS[0][0];
-        const real cx1 = DS[0][0] + DS[0][1];
-        const real cy0 = DS[1][0];
-        const real cy1 = DS[1][0] + DS[1][1];
+        C[a][0] = DS[a][0];
+        C[a][1] = -DS[a][2];
+    }
+    bool crossed = false;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            sink(0, 0, j, 0, q[0] * cx0 * hy[j]);
-            sink(0, 1, j, 0, q[0] * cx1 * hy[j]);
+    for (int a = 0; a < DIM; ++a) crossed = crossed || dc[a] != 0;
+    if (DIM == 2) {
+        // J_x(k, l) = qx C_x[k] h_y[l];  J_y(k, l) = qy h_x[k] C_y[l];
+        // J_z(k, l) = qz (S0x[k] h_y[l] + DSx[k] g_y[l])
+        const real ax = q[0] * C[0][0], ay = q[1] * C[1][0];
+        sink.add(0, 0, 0, 0, ax * h[1][0]);
+        sink.add(0, 0, 1, 0, ax * h[1][1]);
+        sink.add(1, 0, 0, 0, ay * h[0][0]);
+        sink.add(1, 1, 0, 0, ay * h[0][1]);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+                sink.add(2, k, l, 0, qz2d * (S0[0][k] * h[1][l] + DS[0][k] * gq[1][l]));
+        if (crossed) {
+            sink.add_nz(0, 0, 2, 0, ax * h[1][2]);
+            const real bx = q[0] * C[0][1];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sink.add_nz(0, 1, l, 0, bx * h[1][l]);
+            sink.add_nz(1, 2, 0, 0, ay * h[0][2]);
+            const real by = q[1] * C[1][1];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sink.add_nz(1, k, 1, 0, by * h[0][k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    if (k == 2 || l == 2)
+                        sink.add_nz(2, k, l, 0, qz2d * (S0[0][k] * h[1][l] + DS[0][k] * gq[1][l]));
         }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            sink(1, i, 0, 0, q[1] * hx[i] * cy0);
-            sink(1, i, 1, 0, q[1] * hx[i] * cy1);
-        }
-        const real third = real(1) / real(3);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const real wz = S0[0][i] * S0[1][j]
-                              + real(0.5) * (DS[0][i] * S0[1][j] + S0[0][i] * DS[1][j])
-                              + third * DS[0][i] * DS[1][j];
-                sink(2, i, j, 0, qz2d * wz);
-            }
         return;
     }
-    // 3D: per component a, weights over the two transverse axes b, c
-    const real third = real(1) / real(3);
+    // 3D: J_a(k, jb, jc) = q_a C_a[k] (S0b[jb] h_c[jc] + DSb[jb] g_c[jc]),
+    // b, c the axes after a in cyclic order
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int b = (a + 1) % 3;
         const int c = (a + 2) % 3;
-        real T[3][3];   // transverse factor over (node of b, node of c)
+        const real qa = q[a] * C[a][0];
 #pragma unroll
-        for (int jb = 0; jb < 3; ++jb)
+        for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-            for (int jc = 0; jc < 3; ++jc)
-                T[jb][jc] = S0[b][jb] * S0[c][jc]
-                          + real(0.5) * (DS[b][jb] * S0[c][jc] + S0[b][jb] * DS[c][jc])
-                          + third * DS[b][jb] * DS[c][jc];
-        const real c0 = DS[a][0];
-        const real c1 = DS[a][0] + DS[a][1];
-#pragma unroll
-        for (int jb = 0; jb < 3; ++jb)
-#pragma unroll
-            for (int jc = 0; jc < 3; ++jc) {
-                int idx0[3], idx1[3];
-                idx0[a] = 0; idx1[a] = 1;
-                idx0[b] = jb; idx1[b] = jb;
-                idx0[c] = jc; idx1[c] = jc;
-                sink(a, idx0[0], idx0[1], idx0[2], q[a] * c0 * T[jb][jc]);
-                sink(a, idx1[0], idx1[1], idx1[2], q[a] * c1 * T[jb][jc]);
+            for (int jc = 0; jc < 2; ++jc) {
+                int idx[3];
+                idx[a] = 0;
+                idx[b] = jb;
+                idx[c] = jc;
+                sink.add(a, idx[0], idx[1], idx[2],
+                         qa * (S0[b][jb] * h[c][jc] + DS[b][jb] * gq[c][jc]));
             }
+    }
+    if (crossed) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b = (a + 1) % 3;
+            const int c = (a + 2) % 3;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const real qa = q[a] * C[a][k];
+#pragma unroll
+                for (int jb = 0; jb < 3; ++jb)
+#pragma unroll
+                    for (int jc = 0; jc < 3; ++jc) {
+                        if (k == 0 && jb < 2 && jc < 2) continue;
+                        int idx[3];
+                        idx[a] = k;
+                        idx[b] = jb;
+                        idx[c] = jc;
+                        sink.add_nz(a, idx[0], idx[1], idx[2],
+                                    qa * (S0[b][jb] * h[c][jc] + DS[b][jb] * gq[c][jc]));
+                    }
+            }
+        }
     }
 }
 

@@ -14,9 +14,12 @@ struct TileJ {
     int Hx, Hxy, H;
     int o;   // offset of the stencil's base node
     template <typename real>
-    __device__ inline void operator()(int c, int i, int j, int k, real v) const {
-        if (v != real(0))
-            atomicAdd(base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i, (acc_t)v);
+    __device__ inline void add(int c, int i, int j, int k, real v) const {
+        atomicAdd(base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i, (acc_t)v);
+    }
+    template <typename real>
+    __device__ inline void add_nz(int c, int i, int j, int k, real v) const {
+        if (v != real(0)) add(c, i, j, k, v);
     }
 };
 
@@ -27,8 +30,11 @@ struct GlobalJ {
     int n[3];
     int b[3];  // absolute base node
     template <typename real>
-    __device__ inline void operator()(int c, int i, int j, int k, real v) const {
-        if (v == real(0)) return;
+    __device__ inline void add_nz(int c, int i, int j, int k, real v) const {
+        if (v != real(0)) add(c, i, j, k, v);
+    }
+    template <typename real>
+    __device__ inline void add(int c, int i, int j, int k, real v) const {
         const int ix = wrap_index(b[0] + i, n[0]);
         const int iy = wrap_index(b[1] + j, n[1]);
         const int iz = DIM == 3 ? wrap_index(b[2] + k, n[2]) : 0;
@@ -209,25 +215,47 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
         __syncthreads();
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
 
+        // Software pipeline: the next particle of this thread is loaded while
+        // the current one is pushed.
+        int cell_n = 0;
+        real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
+             s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
+        auto load = [&](int i) {
+            const uint32_t bi = (uint32_t)(start + i) * 4u;
+            const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
+            cell_n = ldo(p.cell, bi);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) o_n[a] = ldo(p.off[a], br);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u_n[a] = ldo(p.u[a], br);
+                s_n[a] = ldo(p.s[a], br);
+            }
+            w_n = ldo(p.w, br);
+        };
+        if ((int)threadIdx.x < n) load(threadIdx.x);
+
         for (int base = 0; base < n; base += kBlock) {
             const int i = base + threadIdx.x;
             const bool active = i < n;
-            const long long pi = (long long)start + i;
+            const uint32_t bi = (uint32_t)(start + i) * 4u;
+            const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
+            const int cell0 = cell_n;
+            real o[3], u[3], s[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                o[a] = o_n[a];
+                u[a] = u_n[a];
+                s[a] = s_n[a];
+            }
+            const real wgt = w_n;
+            if (i + kBlock < n) load(i + kBlock);
+
             bool leave = false;
-            int newcell = 0;
-            real o[3] = {real(0), real(0), real(0)}, u[3], s[3], wgt = real(0);
+            int newcell = cell0;
             if (active) {
                 int c[3];
-                unpack_cell<DIM>(p.cell[pi], c[0], c[1], c[2]);
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) o[a] = p.off[a][pi];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    u[a] = p.u[a][pi];
-                    s[a] = p.s[a][pi];
-                }
-                wgt = p.w[pi];
-
+                unpack_cell<DIM>(cell0, c[0], c[1], c[2]);
                 int l[3] = {c[0] - org[0], c[1] - org[1], DIM == 3 ? c[2] - org[2] : 0};
                 Stencil1<real> st[3];
 #pragma unroll
@@ -255,22 +283,24 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
                     }
                     TileJ<acc_t, DIM> sink{Jl, Hx, Hxy, H,
                                            (DIM == 3 ? (b[2] + 1) * Hxy : 0) + (b[1] + 1) * Hx + (b[0] + 1)};
-                    esirkepov<real, DIM>(S0, S1, q, Z * wgt * u[2] * ig, sink);
+                    esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
                 }
-                int nc[3];
+                if (dc[0] | dc[1] | dc[2]) {
+                    int nc[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    nc[a] = c[a];
-                    if (a < DIM) {
-                        const int nl = l[a] + dc[a];
-                        // along an axis with one tile the wrap comes back in
-                        leave = leave || (g.nt[a] > 1 && (nl < 0 || nl >= ext[a]));
-                        nc[a] = c[a] + dc[a];
-                        if (nc[a] < 0) nc[a] += g.n[a];
-                        if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
+                    for (int a = 0; a < 3; ++a) {
+                        nc[a] = c[a];
+                        if (a < DIM) {
+                            const int nl = l[a] + dc[a];
+                            // along an axis with one tile the wrap comes back in
+                            leave = leave || (g.nt[a] > 1 && (nl < 0 || nl >= ext[a]));
+                            nc[a] = c[a] + dc[a];
+                            if (nc[a] < 0) nc[a] += g.n[a];
+                            if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
+                        }
                     }
+                    newcell = pack_cell<DIM>(nc[0], nc[1], nc[2]);
                 }
-                newcell = pack_cell<DIM>(nc[0], nc[1], nc[2]);
             }
 
             const unsigned long long m = __ballot(leave);
@@ -296,19 +326,20 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
                         lv.s[a][L] = s[a];
                     }
                     lv.w[L] = wgt;
-                    lv.id[L] = p.id[pi];
+                    lv.id[L] = ldo(p.id, bi);
                     lv.sp[L] = sp;
                     seg.holes[start + hbase + rank] = i;
                 }
             }
             if (active && !leave) {
-                p.cell[pi] = newcell;
+                // the cell word only changes when the particle crossed a cell edge
+                if (newcell != cell0) sto(p.cell, bi, newcell);
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) p.off[a][pi] = o[a];
+                for (int a = 0; a < DIM; ++a) sto(p.off[a], br, o[a]);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    p.u[a][pi] = u[a];
-                    p.s[a][pi] = s[a];
+                    sto(p.u[a], br, u[a]);
+                    sto(p.s[a], br, s[a]);
                 }
             }
         }
@@ -402,7 +433,7 @@ k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict
                 sink.b[a] = c[a] + shape_pair(o0[a], o[a], dc[a], S0[a], S1[a]);
                 q[a] = -Z * wgt * k.d_dt[a];
             }
-            esirkepov<real, DIM>(S0, S1, q, Z * wgt * u[2] * ig, sink);
+            esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
         }
         int nc[3];
 #pragma unroll
