@@ -60,7 +60,7 @@ size_t lds_need(const int T[3], int ndim) {
     Geom g{};
     g.ndim = ndim;
     for (int a = 0; a < 3; ++a) g.T[a] = T[a];
-    return tile_lds_bytes<real, acc_t>(g);
+    return tile_lds_bytes<real, acc_t>(g, 0);
 }
 
 Status resolve_config(const pic_config* cfg, const pic_state* init, Resolved& R) {
@@ -209,6 +209,14 @@ private:
     Status alloc_store(PArrays<real>& a, long long cap, bool with_species);
     void free_store(PArrays<real>& a);
     Status repack();
+    Status check_lds() {
+        const size_t lds = use_acc64_ ? tile_lds_bytes<real, double>(g_, seg_.max_chunks)
+                                      : tile_lds_bytes<real, real>(g_, seg_.max_chunks);
+        if (lds > 64 * 1024)
+            return fail(PIC_ECAPACITY, "a tile segment of %d slots needs %zu bytes of shared memory "
+                        "(max 65536); use smaller tiles", seg_.max_chunks * 64, lds);
+        return Status{};
+    }
     Status reduce(int mode, const ReduceArgs& ra, double* host_acc);
     Status compute_rho();
     Status residual_max(double* out);
@@ -306,7 +314,8 @@ static long long round_up(long long v, long long m) { return (v + m - 1) / m * m
 
 // Slots of the particle store: the kernels address a slot's FP64 values
 // with a 32-bit byte offset, so 2^29 slots at most.
-constexpr long long kMaxSlots = 1LL << 29;
+constexpr long long kMaxSlots = (1LL << 29) - 64;
+constexpr long long kSpareSlots = 64;   // write targets of masked-off lanes
 
 static long long seg_capacity(long long count, double slack) {
     return round_up((long long)std::ceil(count * (1.0 + slack)) + 32, 32);
@@ -430,8 +439,17 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         if (cap_total_ > kMaxSlots) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^29 slots");
     }
 
+    seg_.dummy = (int)cap_total_;
+    {
+        long long maxcap = 0;
+        for (int sg = 0; sg < nseg_; ++sg) maxcap = std::max<long long>(maxcap, h_cap[sg]);
+        seg_.max_chunks = (int)((maxcap + 63) / 64);
+        Status L = check_lds();
+        if (L.code) return L;
+    }
+
     // ---- device allocations
-    Status S = alloc_store(p_, cap_total_, false);
+    Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
     if (S.code) return S;
     S = alloc_store(lv_, std::max(npart_, 1LL), true);
     if (S.code) return S;
@@ -648,8 +666,17 @@ Status Engine<real, DIM>::repack() {
         total += cp;
         if (total > kMaxSlots) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^29 slots");
     }
+    {
+        long long maxcap = 0;
+        for (int sg = 0; sg < nseg_; ++sg) maxcap = std::max<long long>(maxcap, ncap[sg]);
+        const int saved = seg_.max_chunks;
+        seg_.max_chunks = (int)((maxcap + 63) / 64);
+        Status L = check_lds();
+        seg_.max_chunks = saved;
+        if (L.code) return L;
+    }
     PArrays<real> np{};
-    Status S = alloc_store(np, total, false);
+    Status S = alloc_store(np, total + kSpareSlots, false);
     if (S.code) return S;
     int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     int32_t* holes = (int32_t*)dalloc(total * sizeof(int32_t));
@@ -676,6 +703,12 @@ Status Engine<real, DIM>::repack() {
     seg_.srclist = srcl;
     seg_.slotflag = flags;
     cap_total_ = total;
+    seg_.dummy = (int)total;
+    {
+        long long maxcap = 0;
+        for (int sg = 0; sg < nseg_; ++sg) maxcap = std::max<long long>(maxcap, ncap[sg]);
+        seg_.max_chunks = (int)((maxcap + 63) / 64);
+    }
     h_ctr_[CTR_STASH] = 0;
     repacks_++;
     return Status{};

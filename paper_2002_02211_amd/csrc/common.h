@@ -67,6 +67,9 @@ struct Segs {
     int32_t* holes;     // slot indices vacated by leavers (per segment, from start)
     int32_t* srclist;   // compaction scratch (per segment, from start)
     uint8_t* slotflag;  // compaction scratch, one byte per slot, kept zero
+    int dummy;          // first of 64 spare slots past the last segment; masked-off
+                        // lanes store there so every lane issues the same stores
+    int max_chunks;     // ceil(largest segment capacity / 64)
 };
 
 // Device counters (int32 unless noted), cleared at init.

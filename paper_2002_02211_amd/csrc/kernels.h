@@ -8,7 +8,7 @@ namespace spinpic {
 using freal = double;   // grid fields E, B, J
 
 template <typename real, typename acc_t>
-size_t tile_lds_bytes(const Geom& g);
+size_t tile_lds_bytes(const Geom& g, int max_chunks);
 
 template <typename real, typename acc_t, int DIM>
 hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,

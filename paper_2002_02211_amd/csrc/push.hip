@@ -45,12 +45,13 @@ struct GlobalJ {
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 template <typename real, typename acc_t>
-size_t tile_lds_bytes(const Geom& g) {
+size_t tile_lds_bytes(const Geom& g, int max_chunks) {
     const int Gz = g.ndim == 3 ? g.T[2] + 2 : 1;
     const int Hz = g.ndim == 3 ? g.T[2] + 3 : 1;
     const size_t G = (size_t)(g.T[0] + 2) * (g.T[1] + 2) * Gz;
     const size_t H = (size_t)(g.T[0] + 3) * (g.T[1] + 3) * Hz;
-    return align16(6 * G * sizeof(real)) + 3 * H * sizeof(acc_t);
+    return align16(6 * G * sizeof(real)) + align16(3 * H * sizeof(acc_t)) +
+           (size_t)(max_chunks + 4) * sizeof(unsigned long long);
 }
 
 // Wrap an index that is at most a few periods outside [0, n).
@@ -176,6 +177,9 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     const int Hxy = Hx * Hy, H = Hxy * Hz;
     real* F = reinterpret_cast<real*>(smem);
     acc_t* Jl = reinterpret_cast<acc_t*>(smem + align16((size_t)6 * G * sizeof(real)));
+    // one ballot of leavers per 64-particle chunk of the current segment
+    unsigned long long* leavemask = reinterpret_cast<unsigned long long*>(
+        smem + align16((size_t)6 * G * sizeof(real)) + align16((size_t)3 * H * sizeof(acc_t)));
 
     // stage E and B: each thread owns one x position of several rows
     {
@@ -207,16 +211,21 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     const int lane = threadIdx.x & 63;
     const real half_dt = real(0.5) * k.dt;
 
+    const int wave = threadIdx.x >> 6;
+    const uint32_t dummy_i = (uint32_t)(seg.dummy + lane) * 4u;
+    const uint32_t dummy_r = (uint32_t)(seg.dummy + lane) * (uint32_t)sizeof(real);
+
     for (int sp = 0; sp < g.nsp; ++sp) {
         const int sid = t * g.nsp + sp;
         const int start = seg.start[sid];
         const int n = seg.count[sid];
-        if (threadIdx.x == 0) s_nleave = 0;
-        __syncthreads();
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
 
         // Software pipeline: the next particle of this thread is loaded while
-        // the current one is pushed.
+        // the current one is pushed.  Every lane issues the same loads and
+        // stores in every iteration (clamped load index, masked-off lanes
+        // storing into the spare slots), so the wait for the prefetched data
+        // does not also wait for this iteration's stores to complete.
         int cell_n = 0;
         real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
              s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
@@ -233,13 +242,11 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
             }
             w_n = ldo(p.w, br);
         };
-        if ((int)threadIdx.x < n) load(threadIdx.x);
+        if (n > 0) load(min((int)threadIdx.x, n - 1));
 
         for (int base = 0; base < n; base += kBlock) {
             const int i = base + threadIdx.x;
             const bool active = i < n;
-            const uint32_t bi = (uint32_t)(start + i) * 4u;
-            const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
             const int cell0 = cell_n;
             real o[3], u[3], s[3];
 #pragma unroll
@@ -249,7 +256,7 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
                 s[a] = s_n[a];
             }
             const real wgt = w_n;
-            if (i + kBlock < n) load(i + kBlock);
+            if (base + kBlock < n) load(min(i + kBlock, n - 1));
 
             bool leave = false;
             int newcell = cell0;
@@ -303,44 +310,48 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
                 }
             }
 
-            const unsigned long long m = __ballot(leave);
-            if (m) {
-                const int cnt = __popcll(m);
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                int lbase = 0, hbase = 0;
-                if (lane == leader) {
-                    lbase = atomicAdd(&ctr[slot], cnt);
-                    hbase = atomicAdd(&s_nleave, cnt);
-                }
-                lbase = __shfl(lbase, leader);
-                hbase = __shfl(hbase, leader);
-                if (leave) {
-                    const int L = lbase + rank;
-                    lv.cell[L] = newcell;
+            // Every particle, leaver or not, is written back to its own slot
+            // (a leaver's slot becomes a hole that the tail fills later); the
+            // cell word only where it changed.
+            const uint32_t bi = active ? (uint32_t)(start + i) * 4u : dummy_i;
+            const uint32_t br = active ? (uint32_t)(start + i) * (uint32_t)sizeof(real) : dummy_r;
+            sto(p.cell, newcell != cell0 ? bi : dummy_i, newcell);
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) lv.off[a][L] = o[a];
+            for (int a = 0; a < DIM; ++a) sto(p.off[a], br, o[a]);
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        lv.u[a][L] = u[a];
-                        lv.s[a][L] = s[a];
-                    }
-                    lv.w[L] = wgt;
-                    lv.id[L] = ldo(p.id, bi);
-                    lv.sp[L] = sp;
-                    seg.holes[start + hbase + rank] = i;
-                }
+            for (int a = 0; a < 3; ++a) {
+                sto(p.u[a], br, u[a]);
+                sto(p.s[a], br, s[a]);
             }
-            if (active && !leave) {
-                // the cell word only changes when the particle crossed a cell edge
-                if (newcell != cell0) sto(p.cell, bi, newcell);
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) sto(p.off[a], br, o[a]);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    sto(p.u[a], br, u[a]);
-                    sto(p.s[a], br, s[a]);
-                }
+            const unsigned long long m = __ballot(leave);
+            if (lane == 0) leavemask[(base >> 6) + wave] = m;
+        }
+        __syncthreads();
+
+        // Leavers: copy each from its slot to the leaver store and record the
+        // slot as a hole.
+        if (threadIdx.x == 0) s_nleave = 0;
+        __syncthreads();
+        const int nchunks = (n + 63) >> 6;
+        for (int ch = wave; ch < nchunks; ch += kBlock / 64) {
+            const unsigned long long m = leavemask[ch];
+            if (m == 0) continue;
+            const int cnt = __popcll(m);
+            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+            int lbase = 0, hbase = 0;
+            if (lane == 0) {
+                lbase = atomicAdd(&ctr[slot], cnt);
+                hbase = atomicAdd(&s_nleave, cnt);
+            }
+            lbase = __shfl(lbase, 0);
+            hbase = __shfl(hbase, 0);
+            if ((m >> lane) & 1ull) {
+                const int i = (ch << 6) + lane;
+                const long long pi = (long long)start + i;
+                const int L = lbase + rank;
+                copy_particle(p, pi, lv, L, DIM);
+                lv.sp[L] = sp;
+                seg.holes[start + hbase + rank] = i;
             }
         }
         __syncthreads();
@@ -509,7 +520,7 @@ template <typename real, typename acc_t, int DIM>
 hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,
                              const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
                              const Fields<freal>& f, int deposit, hipStream_t stream) {
-    const size_t lds = tile_lds_bytes<real, acc_t>(g);
+    const size_t lds = tile_lds_bytes<real, acc_t>(g, seg.max_chunks);
     const int grid = ((g.ntiles + 7) >> 3) * 8;
     hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM>), dim3(grid), dim3(kBlock), lds, stream,
                        g, k, p, seg, lv, ctr, slot, f, deposit);
@@ -545,9 +556,9 @@ SPINPIC_INST_PUSH(float, double, 2)
 SPINPIC_INST_PUSH(float, double, 3)
 SPINPIC_INST_PUSH(double, double, 2)
 SPINPIC_INST_PUSH(double, double, 3)
-template size_t tile_lds_bytes<float, float>(const Geom&);
-template size_t tile_lds_bytes<float, double>(const Geom&);
-template size_t tile_lds_bytes<double, double>(const Geom&);
+template size_t tile_lds_bytes<float, float>(const Geom&, int);
+template size_t tile_lds_bytes<float, double>(const Geom&, int);
+template size_t tile_lds_bytes<double, double>(const Geom&, int);
 
 #define SPINPIC_INST_REST(real, DIM)                                                            \
     template hipError_t launch_push_stash<real, DIM>(const Geom&, const Consts<real>&,         \
