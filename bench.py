@@ -1,7 +1,8 @@
 """Throughput of the spin-resolved PIC step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
-                    [--precision fp32|fp64] [--no-cpu-baseline]
+                    [--precision fp32|fp64] [--no-cpu-baseline] [--no-fp64-compare]
+    python bench.py --traffic-from FETCH.csv WRITE.csv [--workload c2] [--precision fp32]
 
 A step is one full pass of the hot path over every particle: gather, Boris
 push, Thomas-BMT spin rotation, move and Esirkepov deposit (one fused kernel
@@ -9,6 +10,17 @@ per tile), the rebinning of tile leavers, and the Yee field update.  Inputs
 are the seeded synthetic plasma of the workload (default c2: 2D3V,
 4096x1024 cells, electrons and protons at 8 per cell each, 67,108,864
 particles), resident in HBM before timing starts.  Prints one JSON line.
+
+With FP32 particles the same workload is then run again with the FP64 path
+for the same number of steps, and its throughput and the largest difference
+of the polarization vector between the two runs are reported beside.
+
+``--traffic-from`` turns two rocprofv3 counter runs of this script (one with
+``--pmc FETCH_SIZE``, one with ``--pmc WRITE_SIZE``, each with
+``--copy-probe-mib 1024``) into the HBM-traffic record under ``profiles/``
+that the ``roofline.traffic`` field reports while the kernel sources are
+unchanged.  Each counter is scaled by what it reads for the 1 GiB probe
+(fill, then copy) of known size.
 """
 
 import argparse
@@ -59,7 +71,7 @@ def source_hash():
 def measured_traffic(workload, precision, launches_bytes):
     """HBM traffic of the push kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "push_deposit_%s_%s_traffic.json" % (workload, precision))
+    path = traffic_path(workload, precision)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -67,6 +79,76 @@ def measured_traffic(workload, precision, launches_bytes):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def traffic_path(workload, precision):
+    return os.path.join(ROOT, "profiles", "push_deposit_%s_%s_traffic.json" % (workload, precision))
+
+
+def _counter_means(path, counter):
+    """Mean counter value per dispatch, by kernel name (text before '(')."""
+    import csv
+    import re
+    sums = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            name = re.sub(r"\(.*", "", row["Kernel_Name"]).replace("void ", "").strip()
+            tot, n = sums.get(name, (0.0, 0))
+            sums[name] = (tot + float(row["Counter_Value"]), n + 1)
+    return {k: (t / n, n) for k, (t, n) in sums.items()}
+
+
+def write_traffic(fetch_csv, write_csv, workload, precision, probe_mib=1024):
+    """Push-kernel HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), calibrated on the probe: the fill kernel writes
+    probe_mib MiB, the copy dispatches read and write probe_mib MiB in all."""
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    probe = probe_mib * 1024.0   # KiB
+    copy = [k for k in fetch if "copyBuffer" in k]
+    fill = [k for k in write if "elementwise_kernel" in k and "Fill" in k]
+    if not copy or not fill:
+        raise SystemExit("probe kernels not found in the counter files")
+    cf_mean, cf_n = fetch[copy[0]]
+    f_fetch = probe / (cf_mean * cf_n)
+    f_write = probe / write[fill[0]][0]
+    push = [k for k in fetch if "k_push_tiles" in k]
+    if len(push) != 1:
+        raise SystemExit("expected one push kernel instantiation, found %s" % push)
+    pf, n_f = fetch[push[0]]
+    pw, n_w = write[push[0]]
+    rec = {"kernel": push[0], "workload": workload, "precision": precision,
+           "source_hash": source_hash(),
+           "fetch_kib_per_dispatch": pf, "write_kib_per_dispatch": pw,
+           "dispatches": [n_f, n_w],
+           "fetch_scale": f_fetch, "write_scale": f_write,
+           "fetch_bytes_per_launch": pf * 1024 * f_fetch,
+           "write_bytes_per_launch": pw * 1024 * f_write}
+    rec["bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    others = {}
+    for k in sorted(set(fetch) & set(write)):
+        if k.startswith("spinpic::"):
+            others[k] = {"fetch_bytes": fetch[k][0] * 1024 * f_fetch,
+                         "write_bytes": write[k][0] * 1024 * f_write, "dispatches": fetch[k][1]}
+    rec["all_kernels"] = others
+    with open(traffic_path(workload, precision), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({k: rec[k] for k in ("kernel", "fetch_scale", "write_scale",
+                                          "fetch_bytes_per_launch", "write_bytes_per_launch",
+                                          "bytes_per_launch")}))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def cpu_baseline(spec, state, sample_per_species):
@@ -89,8 +171,31 @@ def cpu_baseline(spec, state, sample_per_species):
     del sim
     return {"value": n / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
             "sample": "%d particles (%d per species, first rows of the same seeded %s state), "
-                      "one gather+push+spin+deposit pass, FP64 NumPy, %.1f s"
-                      % (n, sample_per_species, spec["name"], dt)}
+                      "one gather+push+spin+deposit pass, FP64 NumPy, one thread of %s, %.1f s"
+                      % (n, sample_per_species, spec["name"], cpu_model(), dt)}
+
+
+def run_gpu(S, spec, state, precision, acc, warmup, steps):
+    """Initialize, warm up, time `steps` steps; returns (sim, elapsed s, timers)."""
+    import torch
+    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc)
+    t0 = time.time()
+    sim = S.Simulation(cfg, state["particles"], state["fields"])
+    torch.cuda.synchronize()
+    print("[bench] %s init (sort + upload) %.1f s" % (precision, time.time() - t0),
+          file=sys.stderr, flush=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    print("[bench] %s warmup done" % precision, file=sys.stderr, flush=True)
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = sim.timing_read()
+    sim.timing(False)
+    return sim, cfg, elapsed, timers
 
 
 def main():
@@ -103,11 +208,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
                     help="precision of the per-tile shared-memory current sums (FP32 path)")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip the FP64 run of the same workload (FP32 runs only)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the push kernel's traffic record from rocprofv3 counter files and exit")
+    ap.add_argument("--cpu-sample", type=int, default=8_000_000,
                     help="particles per species in the CPU-baseline sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration)")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        import synth
+        spec = synth.preset(args.workload)
+        write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload,
+                      args.precision or spec["precision"])
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -140,25 +256,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    t0 = time.time()
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
-    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc)
-    sim = S.Simulation(cfg, state["particles"], state["fields"])
-    torch.cuda.synchronize()
-    print("[bench] init (sort + upload) %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    sim.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timers = sim.timing_read()
-    sim.timing(False)
+    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps)
     stats = sim.stats()
     P, N = sim.polarization()
     print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s N=%d"
@@ -201,6 +300,21 @@ def main():
     sim.close()
     del sim
     torch.cuda.synchronize()
+
+    if precision == "fp32" and not args.no_fp64_compare:
+        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps)
+        P64, _ = sim64.polarization()
+        sim64.close()
+        del sim64
+        torch.cuda.synchronize()
+        lb64, _, _ = algorithmic_bytes(spec["ndim"], "fp64", npart, ncells)
+        t64 = tm64["push_deposit"][0] / 1e3 / max(tm64["push_deposit"][1], 1)
+        result["fp64_compare"] = {
+            "value": npart * args.steps / el64, "unit": "pushes/s",
+            "ms_per_step": el64 / args.steps * 1e3,
+            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "dP_max_fp32_vs_fp64": float(max(abs(a - b) for a, b in zip(P, P64))),
+            "after_steps": args.warmup + args.steps}
 
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, min(p.shape[0] for p in state["particles"]))
