@@ -458,9 +458,6 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     seg_.start = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     seg_.cap = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     seg_.count = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
-    seg_.holes = (int32_t*)dalloc(cap_total_ * sizeof(int32_t));
-    seg_.srclist = (int32_t*)dalloc(cap_total_ * sizeof(int32_t));
-    seg_.slotflag = (uint8_t*)dalloc(cap_total_);
     for (int a = 0; a < 3; ++a) {
         f_.E[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
         f_.B[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
@@ -475,8 +472,8 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     resid_blocks_ = (int)std::min<long long>(4096, (g_.ncells + kBlock - 1) / kBlock);
     blockmax_ = (double*)dalloc(resid_blocks_ * sizeof(double));
     nf_flag_ = (int32_t*)dalloc(sizeof(int32_t));
-    bool ok = seg_.start && seg_.cap && seg_.count && seg_.holes && seg_.srclist &&
-              seg_.slotflag && ctr_ && moved_ && acc_ && rho_ && ref_ && blockmax_ && nf_flag_;
+    bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && acc_ && rho_ && ref_ &&
+              blockmax_ && nf_flag_;
     for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
     if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
     HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
@@ -540,7 +537,6 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     HIP_OR_FAIL(hipMemcpyAsync(seg_.start, h_start.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
     HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, h_cap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
     HIP_OR_FAIL(hipMemcpyAsync(seg_.count, h_count.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
-    HIP_OR_FAIL(hipMemsetAsync(seg_.slotflag, 0, (size_t)cap_total_, stream_));
     HIP_OR_FAIL(hipMemsetAsync(ctr_, 0, CTR_NCTR * sizeof(int32_t), stream_));
     HIP_OR_FAIL(hipMemsetAsync(moved_, 0, sizeof(unsigned long long), stream_));
 
@@ -679,29 +675,19 @@ Status Engine<real, DIM>::repack() {
     Status S = alloc_store(np, total + kSpareSlots, false);
     if (S.code) return S;
     int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
-    int32_t* holes = (int32_t*)dalloc(total * sizeof(int32_t));
-    int32_t* srcl = (int32_t*)dalloc(total * sizeof(int32_t));
-    uint8_t* flags = (uint8_t*)dalloc(total);
-    if (!d_nstart || !holes || !srcl || !flags) return fail(PIC_ENOMEM, "repack allocation failed");
+    if (!d_nstart) return fail(PIC_ENOMEM, "repack allocation failed");
     HIP_OR_FAIL(hipMemcpyAsync(d_nstart, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
     HIP_OR_FAIL((launch_repack_segments<real>(p_, np, seg_.start, d_nstart, seg_.count, nseg_, DIM, stream_)));
     HIP_OR_FAIL(hipMemcpyAsync(seg_.start, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
     HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, ncap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
-    HIP_OR_FAIL(hipMemsetAsync(flags, 0, (size_t)total, stream_));
     // move the overflow particles into their tiles: the insertion kernel run
     // over the overflow store, which now always finds room
     HIP_OR_FAIL((launch_insert<real, DIM>(g_, np, seg_, st_, st_, ctr_, CTR_STASH, moved_, 256, stream_)));
     HIP_OR_FAIL(hipMemsetAsync(ctr_ + CTR_STASH, 0, sizeof(int32_t), stream_));
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
     free_store(p_);
-    dfree(seg_.holes);
-    dfree(seg_.srclist);
-    dfree(seg_.slotflag);
     dfree(d_nstart);
     p_ = np;
-    seg_.holes = holes;
-    seg_.srclist = srcl;
-    seg_.slotflag = flags;
     cap_total_ = total;
     seg_.dummy = (int)total;
     {

@@ -64,9 +64,6 @@ struct Segs {
     int32_t* start;     // first slot of each (tile, species) segment
     int32_t* cap;       // slots reserved for it
     int32_t* count;     // particles it holds
-    int32_t* holes;     // slot indices vacated by leavers (per segment, from start)
-    int32_t* srclist;   // compaction scratch (per segment, from start)
-    uint8_t* slotflag;  // compaction scratch, one byte per slot, kept zero
     int dummy;          // first of 64 spare slots past the last segment; masked-off
                         // lanes store there so every lane issues the same stores
     int max_chunks;     // ceil(largest segment capacity / 64)

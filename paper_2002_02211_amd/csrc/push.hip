@@ -42,6 +42,15 @@ struct GlobalJ {
     }
 };
 
+// One particle's state in registers.
+template <typename real>
+struct PRegs {
+    int cell;
+    real o[3], u[3], s[3], w;
+};
+
+constexpr int kPairCap = 256;   // compaction pairs per round
+
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 template <typename real, typename acc_t>
@@ -51,7 +60,8 @@ size_t tile_lds_bytes(const Geom& g, int max_chunks) {
     const size_t G = (size_t)(g.T[0] + 2) * (g.T[1] + 2) * Gz;
     const size_t H = (size_t)(g.T[0] + 3) * (g.T[1] + 3) * Hz;
     return align16(6 * G * sizeof(real)) + align16(3 * H * sizeof(acc_t)) +
-           (size_t)(max_chunks + 4) * sizeof(unsigned long long);
+           align16((size_t)(max_chunks + 4) * sizeof(unsigned long long)) +
+           align16((size_t)(max_chunks + 4) * sizeof(int)) + (size_t)kPairCap * sizeof(int);
 }
 
 // Wrap an index that is at most a few periods outside [0, n).
@@ -61,80 +71,30 @@ __device__ inline int wrap_near(int i, int n) {
     return i;
 }
 
-// Exclusive prefix count of pred over the workgroup; *total gets the sum.
-// Every thread of the workgroup must call it.
-__device__ inline int block_exclusive_count(bool pred, int* total) {
-    __shared__ int wsum[kBlock / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long m = __ballot(pred);
-    const int rank = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[wv] = __popcll(m);
-    __syncthreads();
-    int before = 0, sum = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        before += w < wv ? wsum[w] : 0;
-        sum += wsum[w];
-    }
-    __syncthreads();
-    *total = sum;
-    return before + rank;
-}
-
+// Copy particle i of one store to slot j of another (or the same) store.
+// Every value is loaded before the first store, so the loads go out
+// together instead of one round trip per array.
 template <typename real>
 __device__ inline void copy_particle(const PArrays<real>& from, long long i, const PArrays<real>& to,
                                      long long j, int ndim) {
-    to.cell[j] = from.cell[i];
-    for (int a = 0; a < ndim; ++a) to.off[a][j] = from.off[a][i];
+    const int32_t cell = from.cell[i], id = from.id[i];
+    real o[3], u[3], s[3];
+    for (int a = 0; a < 3; ++a) o[a] = a < ndim ? from.off[a][i] : real(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        to.u[a][j] = from.u[a][i];
-        to.s[a][j] = from.s[a][i];
+        u[a] = from.u[a][i];
+        s[a] = from.s[a][i];
     }
-    to.w[j] = from.w[i];
-    to.id[j] = from.id[i];
-}
-
-// Close the holes a segment's leavers left: with L leavers out of n the
-// segment shrinks to n - L slots, and the particles still present in the
-// tail [n - L, n) move into the holes below n - L.  Runs in the workgroup
-// that just pushed the segment; its stores are visible to it after the
-// barrier.  Every thread must call it.
-template <typename real>
-__device__ void compact_segment(const PArrays<real>& p, const Segs& seg, int start, int n, int L,
-                                int ndim) {
-    const int nn = n - L;
-    for (int t = threadIdx.x; t < L; t += kBlock) {
-        const int h = seg.holes[start + t];
-        if (h >= nn) seg.slotflag[start + h] = 1;
+    const real w = from.w[i];
+    to.cell[j] = cell;
+    for (int a = 0; a < ndim; ++a) to.off[a][j] = o[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        to.u[a][j] = u[a];
+        to.s[a][j] = s[a];
     }
-    __syncthreads();
-    int done = 0, total = 0;
-    for (int b = 0; b < L; b += kBlock) {
-        const int j = b + threadIdx.x;
-        const bool src = j < L && seg.slotflag[start + nn + j] == 0;
-        const int rank = block_exclusive_count(src, &total);
-        if (src) seg.srclist[start + done + rank] = nn + j;
-        done += total;
-    }
-    __syncthreads();
-    done = 0;
-    for (int b = 0; b < L; b += kBlock) {
-        const int t = b + threadIdx.x;
-        const int h = t < L ? seg.holes[start + t] : n;
-        const bool front = h < nn;
-        const int rank = block_exclusive_count(front, &total);
-        if (front) {
-            const int from = seg.srclist[start + done + rank];
-            copy_particle(p, (long long)start + from, p, (long long)start + h, ndim);
-        }
-        done += total;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < L; t += kBlock) {
-        const int h = seg.holes[start + t];
-        if (h >= nn) seg.slotflag[start + h] = 0;
-    }
+    to.w[j] = w;
+    to.id[j] = id;
 }
 
 // One workgroup per tile.  The tile's E and B, with one guard cell on each
@@ -150,7 +110,7 @@ __global__ void __launch_bounds__(kBlock)
 k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
              int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_nleave;
+    __shared__ int s_nleave, s_lbase;
 
     // the other step's leaver counter is free again: clear it for the next step
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
@@ -177,9 +137,14 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     const int Hxy = Hx * Hy, H = Hxy * Hz;
     real* F = reinterpret_cast<real*>(smem);
     acc_t* Jl = reinterpret_cast<acc_t*>(smem + align16((size_t)6 * G * sizeof(real)));
-    // one ballot of leavers per 64-particle chunk of the current segment
-    unsigned long long* leavemask = reinterpret_cast<unsigned long long*>(
-        smem + align16((size_t)6 * G * sizeof(real)) + align16((size_t)3 * H * sizeof(acc_t)));
+    // one ballot of leavers per 64-particle chunk of the current segment,
+    // their exclusive prefix counts, and the source slots of one round of
+    // compaction
+    const size_t lm_off = align16((size_t)6 * G * sizeof(real)) + align16((size_t)3 * H * sizeof(acc_t));
+    unsigned long long* leavemask = reinterpret_cast<unsigned long long*>(smem + lm_off);
+    int* lprefix = reinterpret_cast<int*>(smem + lm_off + align16((size_t)(seg.max_chunks + 4) * 8));
+    int* srcpos = reinterpret_cast<int*>(smem + lm_off + align16((size_t)(seg.max_chunks + 4) * 8) +
+                                         align16((size_t)(seg.max_chunks + 4) * 4));
 
     // stage E and B: each thread owns one x position of several rows
     {
@@ -217,46 +182,43 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
 
     for (int sp = 0; sp < g.nsp; ++sp) {
         const int sid = t * g.nsp + sp;
-        const int start = seg.start[sid];
-        const int n = seg.count[sid];
+        const int start = __builtin_amdgcn_readfirstlane(seg.start[sid]);
+        const int n = __builtin_amdgcn_readfirstlane(seg.count[sid]);
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
 
-        // Software pipeline: the next particle of this thread is loaded while
-        // the current one is pushed.  Every lane issues the same loads and
-        // stores in every iteration (clamped load index, masked-off lanes
-        // storing into the spare slots), so the wait for the prefetched data
-        // does not also wait for this iteration's stores to complete.
-        int cell_n = 0;
-        real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
-             s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
-        auto load = [&](int i) {
+        // Software pipeline two particles deep: a thread's particle for pass
+        // j + 2 is loaded before pass j is pushed and stored.  Loads and stores
+        // retire in issue order, so waiting for a load also waits for every
+        // store issued before it; loading two passes ahead leaves the stores
+        // of a pass two passes of arithmetic to drain to memory.  Every lane
+        // issues the same loads (index clamped to the last particle) and
+        // stores (masked-off lanes write the spare slots) in every pass.
+        PRegs<real> S0, S1, S2;
+        auto load = [&](PRegs<real>& R, int i) {
             const uint32_t bi = (uint32_t)(start + i) * 4u;
             const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
-            cell_n = ldo(p.cell, bi);
+            R.cell = ldo(p.cell, bi);
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) o_n[a] = ldo(p.off[a], br);
+            for (int a = 0; a < DIM; ++a) R.o[a] = ldo(p.off[a], br);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                u_n[a] = ldo(p.u[a], br);
-                s_n[a] = ldo(p.s[a], br);
+                R.u[a] = ldo(p.u[a], br);
+                R.s[a] = ldo(p.s[a], br);
             }
-            w_n = ldo(p.w, br);
+            R.w = ldo(p.w, br);
         };
-        if (n > 0) load(min((int)threadIdx.x, n - 1));
-
-        for (int base = 0; base < n; base += kBlock) {
+        auto pass = [&](int base, const PRegs<real>& P) {
             const int i = base + threadIdx.x;
             const bool active = i < n;
-            const int cell0 = cell_n;
+            const int cell0 = P.cell;
             real o[3], u[3], s[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                o[a] = o_n[a];
-                u[a] = u_n[a];
-                s[a] = s_n[a];
+                o[a] = a < DIM ? P.o[a] : real(0);
+                u[a] = P.u[a];
+                s[a] = P.s[a];
             }
-            const real wgt = w_n;
-            if (base + kBlock < n) load(min(i + kBlock, n - 1));
+            const real wgt = P.w;
 
             bool leave = false;
             int newcell = cell0;
@@ -325,38 +287,114 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
             }
             const unsigned long long m = __ballot(leave);
             if (lane == 0) leavemask[(base >> 6) + wave] = m;
+        };
+        // three register sets in rotation (unrolled by three), so that no set
+        // is copied and the loads stay two passes ahead of their use
+        auto phase = [&](int base, const PRegs<real>& P, PRegs<real>& L) {
+            load(L, min(base + 2 * kBlock + (int)threadIdx.x, n - 1));
+            pass(base, P);
+        };
+        // The prologue issues the same sequence of memory operations as a
+        // pass (loads, then one store per array into the spare slots), so
+        // that the loop is entered with the memory counter in its steady
+        // state and the waits inside it can stay loose.  Load indices are
+        // clamped into the segment.  The loop has a single exit (whole
+        // triples of passes); the last one or two passes follow it.
+        uint32_t spare_i = dummy_i, spare_r = dummy_r;
+        asm volatile("" : "+v"(spare_i), "+v"(spare_r));   // keep these 32-bit offsets here
+        auto spare_stores = [&]() {
+            sto(p.cell, spare_i, 0);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) sto(p.off[a], spare_r, real(0));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sto(p.u[a], spare_r, real(0));
+                sto(p.s[a], spare_r, real(0));
+            }
+        };
+        const int npass = (n + kBlock - 1) / kBlock;
+        if (npass > 0) {
+            load(S0, min((int)threadIdx.x, n - 1));
+            spare_stores();
+            load(S1, min((int)threadIdx.x + kBlock, n - 1));
+            spare_stores();
         }
+        int j = 0;
+        for (; j + 3 <= npass; j += 3) {
+            phase(j * kBlock, S0, S2);
+            phase((j + 1) * kBlock, S1, S0);
+            phase((j + 2) * kBlock, S2, S1);
+        }
+        if (j < npass) pass(j * kBlock, S0);
+        if (j + 1 < npass) pass((j + 1) * kBlock, S1);
         __syncthreads();
 
-        // Leavers: copy each from its slot to the leaver store and record the
-        // slot as a hole.
-        if (threadIdx.x == 0) s_nleave = 0;
-        __syncthreads();
+        // Leavers and compaction, from the per-chunk leaver ballots in shared
+        // memory.  Exclusive prefix counts of the ballots give every leaver
+        // its rank in the leaver store (one global reservation per segment),
+        // and every slot a leaver vacated below the segment's new end n - L
+        // the particle that fills it: the one of equal rank among those still
+        // present in the tail [n - L, n).
         const int nchunks = (n + 63) >> 6;
-        for (int ch = wave; ch < nchunks; ch += kBlock / 64) {
-            const unsigned long long m = leavemask[ch];
-            if (m == 0) continue;
-            const int cnt = __popcll(m);
-            const int rank = __popcll(m & ((1ull << lane) - 1ull));
-            int lbase = 0, hbase = 0;
-            if (lane == 0) {
-                lbase = atomicAdd(&ctr[slot], cnt);
-                hbase = atomicAdd(&s_nleave, cnt);
+        if (wave == 0) {
+            int carry = 0;
+            for (int c0 = 0; c0 <= nchunks; c0 += 64) {
+                const int c = c0 + lane;
+                unsigned long long m = 0ull;
+                if (c < nchunks) m = leavemask[c];
+                else if (c == nchunks) leavemask[c] = 0ull;   // read when counting up to slot n
+                const int v = __popcll(m);
+                int x = v;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(x, off);
+                    if (lane >= off) x += y;
+                }
+                if (c <= nchunks) lprefix[c] = carry + x - v;
+                carry += __shfl(x, 63);
             }
-            lbase = __shfl(lbase, 0);
-            hbase = __shfl(hbase, 0);
-            if ((m >> lane) & 1ull) {
-                const int i = (ch << 6) + lane;
-                const long long pi = (long long)start + i;
-                const int L = lbase + rank;
-                copy_particle(p, pi, lv, L, DIM);
-                lv.sp[L] = sp;
-                seg.holes[start + hbase + rank] = i;
+            if (lane == 0) {
+                s_nleave = carry;
+                s_lbase = carry > 0 ? atomicAdd(&ctr[slot], carry) : 0;
             }
         }
         __syncthreads();
         const int L = s_nleave;
-        if (L > 0) compact_segment(p, seg, start, n, L, DIM);
+        if (L > 0) {
+            const int lbase = s_lbase;
+            const int nn = n - L;
+            // leavers among slots [0, x), 0 <= x <= n
+            auto lcount = [&](int x) {
+                const int c = x >> 6;
+                return lprefix[c] + __popcll(leavemask[c] & ((1ull << (x & 63)) - 1ull));
+            };
+            const int pairs = lcount(nn);
+            for (int r0 = 0; r0 == 0 || r0 < pairs; r0 += kPairCap) {
+                for (int q = threadIdx.x; q < L; q += kBlock) {
+                    const int pos = nn + q;
+                    if (!((leavemask[pos >> 6] >> (pos & 63)) & 1ull)) {
+                        const int rank = q - (lcount(pos) - pairs);
+                        if (rank >= r0 && rank < r0 + kPairCap) srcpos[rank - r0] = pos;
+                    }
+                }
+                __syncthreads();
+                for (int ch = wave; ch < nchunks; ch += kBlock / 64) {
+                    const unsigned long long m = leavemask[ch];
+                    if ((m >> lane) & 1ull) {
+                        const int h = (ch << 6) + lane;
+                        const int rank = lprefix[ch] + __popcll(m & ((1ull << lane) - 1ull));
+                        // the leaver is read before its slot is refilled (same thread)
+                        if (r0 == 0) {
+                            copy_particle(p, (long long)start + h, lv, (long long)lbase + rank, DIM);
+                            lv.sp[lbase + rank] = sp;
+                        }
+                        if (h < nn && rank >= r0 && rank < r0 + kPairCap)
+                            copy_particle(p, (long long)start + srcpos[rank - r0], p, (long long)start + h, DIM);
+                    }
+                }
+                __syncthreads();
+            }
+        }
         if (threadIdx.x == 0) seg.count[sid] = n - L;
         __syncthreads();
     }
