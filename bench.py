@@ -175,10 +175,10 @@ def cpu_baseline(spec, state, sample_per_species):
                       % (n, sample_per_species, spec["name"], cpu_model(), dt)}
 
 
-def run_gpu(S, spec, state, precision, acc, warmup, steps):
-    """Initialize, warm up, time `steps` steps; returns (sim, elapsed s, timers)."""
+def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None):
+    """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
     import torch
-    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc)
+    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile)
     t0 = time.time()
     sim = S.Simulation(cfg, state["particles"], state["fields"])
     torch.cuda.synchronize()
@@ -208,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
                     help="precision of the per-tile shared-memory current sums (FP32 path)")
+    ap.add_argument("--tile", default=None,
+                    help="tile shape in cells, e.g. 16,16 or 8,8,6 (default: the library's choice)")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 run of the same workload (FP32 runs only)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -257,7 +259,8 @@ def main():
         del a, b
 
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
-    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps, tile)
     stats = sim.stats()
     P, N = sim.polarization()
     print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s N=%d"
@@ -287,7 +290,7 @@ def main():
                    "particles": npart, "cells": ncells,
                    "precision": "FP32 particles and push; FP64 fields, currents, reductions"
                                 if precision == "fp32" else "FP64",
-                   "tile": list(cfg.tile)[: spec["ndim"]]},
+                   "tile": list(stats["tile"])[: spec["ndim"]]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_push_tiles (gather+Boris+T-BMT+move+Esirkepov deposit)",
@@ -302,7 +305,7 @@ def main():
     torch.cuda.synchronize()
 
     if precision == "fp32" and not args.no_fp64_compare:
-        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps)
+        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile)
         P64, _ = sim64.polarization()
         sim64.close()
         del sim64

@@ -87,7 +87,7 @@ typedef struct {
     int32_t nspecies;    /* 1 .. PIC_MAX_SPECIES */
     pic_species sp[PIC_MAX_SPECIES];
     int32_t tile[3];     /* tile edge in cells per axis; 0 selects the default
-                            (16x16 in 2D, 8x8x8 in 3D FP32, 6x6x6 in 3D FP64) */
+                            (16x16 in 2D, 12x6x6 in 3D FP32, 6x6x6 in 3D FP64) */
     double slack;        /* spare capacity per tile segment as a fraction of its
                             initial population (>= 0; 0 selects 0.25) */
     int32_t flags;       /* PIC_FLAG_* */
@@ -155,7 +155,8 @@ int pic_energy(pic_ctx* ctx, double* out, int32_t cap);
 
 /* Counters since init: out[0] steps, out[1] particles that changed tile,
  * out[2] particles currently in the overflow store, out[3] repacks done,
- * out[4] total particles.  cap >= 5.  Waits. */
+ * out[4] total particles; with cap >= 8 also out[5 .. 7] the tile edge in
+ * cells per axis in use (1 on axes beyond ndim).  cap >= 5.  Waits. */
 int pic_stats(pic_ctx* ctx, int64_t* out, int32_t cap);
 
 /* Per-kernel GPU timing with HIP events on the context's stream.

@@ -113,7 +113,10 @@ Status resolve_config(const pic_config* cfg, const pic_state* init, Resolved& R)
             continue;
         }
         int t = c.tile[a];
-        if (t == 0) t = c.ndim == 2 ? 16 : (c.precision == PIC_FP64 ? 6 : 8);
+        // defaults measured on gfx950: 16 x 16 in 2D; in 3D tiles of 12 x 6 x 6
+        // (FP32 particles) or 6 x 6 x 6 (FP64) fit three workgroups per CU
+        // in shared memory
+        if (t == 0) t = c.ndim == 2 ? 16 : (c.precision == PIC_FP64 ? 6 : (a == 0 ? 12 : 6));
         if (t < 1 || t > 64) return fail(PIC_EINVAL, "tile[%d] = %d outside 1..64", a, c.tile[a]);
         t = std::min(t, R.n[a]);
         R.T[a] = t;
@@ -894,6 +897,7 @@ Status Engine<real, DIM>::stats(int64_t* out, int cap) {
     out[2] = nst;
     out[3] = repacks_;
     out[4] = npart_;
+    for (int a = 0; a < 3 && 5 + a < cap; ++a) out[5 + a] = g_.T[a];
     return Status{};
 }
 

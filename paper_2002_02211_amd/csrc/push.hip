@@ -42,14 +42,8 @@ struct GlobalJ {
     }
 };
 
-// One particle's state in registers.
-template <typename real>
-struct PRegs {
-    int cell;
-    real o[3], u[3], s[3], w;
-};
-
 constexpr int kPairCap = 256;   // compaction pairs per round
+constexpr int kStageRows = 4;   // field rows a thread loads before storing them
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
@@ -146,23 +140,39 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     int* srcpos = reinterpret_cast<int*>(smem + lm_off + align16((size_t)(seg.max_chunks + 4) * 8) +
                                          align16((size_t)(seg.max_chunks + 4) * 4));
 
-    // stage E and B: each thread owns one x position of several rows
+    // stage E and B: each thread owns one x position of several (y, z) rows
+    // and issues the loads of up to kStageRows rows before writing any
     {
         const int rpp = kBlock / Gx;              // rows per pass
         const int r0 = threadIdx.x / Gx;
         const int gx = threadIdx.x - r0 * Gx;
         const long long ix = wrap_near(org[0] - 1 + gx, g.n[0]);
+        const int rows = Gy * Gz;
         if (r0 < rpp) {
-            for (int gz = 0; gz < Gz; ++gz) {
-                const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + gz, g.n[2]) : 0;
-                for (int gy = r0; gy < Gy; gy += rpp) {
-                    const long long iy = wrap_near(org[1] - 1 + gy, g.n[1]);
-                    const long long gi = (iz * g.n[1] + iy) * g.n[0] + ix;
-                    const int li = gz * Gxy + gy * Gx + gx;
+            for (int rb = r0; rb < rows; rb += kStageRows * rpp) {
+                freal v[kStageRows][6];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        F[c * G + li] = (real)f.E[c][gi];
-                        F[(3 + c) * G + li] = (real)f.B[c][gi];
+                for (int q = 0; q < kStageRows; ++q) {
+                    const int row = rb + q * rpp;
+                    if (row < rows) {
+                        const int gz = row / Gy, gy = row - gz * Gy;
+                        const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + gz, g.n[2]) : 0;
+                        const long long iy = wrap_near(org[1] - 1 + gy, g.n[1]);
+                        const long long gi = (iz * g.n[1] + iy) * g.n[0] + ix;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            v[q][c] = f.E[c][gi];
+                            v[q][3 + c] = f.B[c][gi];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kStageRows; ++q) {
+                    const int row = rb + q * rpp;
+                    if (row < rows) {
+                        const int li = row * Gx + gx;
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) F[c * G + li] = (real)v[q][c];
                     }
                 }
             }
@@ -186,39 +196,42 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
         const int n = __builtin_amdgcn_readfirstlane(seg.count[sid]);
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
 
-        // Software pipeline two particles deep: a thread's particle for pass
-        // j + 2 is loaded before pass j is pushed and stored.  Loads and stores
-        // retire in issue order, so waiting for a load also waits for every
-        // store issued before it; loading two passes ahead leaves the stores
-        // of a pass two passes of arithmetic to drain to memory.  Every lane
-        // issues the same loads (index clamped to the last particle) and
-        // stores (masked-off lanes write the spare slots) in every pass.
-        PRegs<real> S0, S1, S2;
-        auto load = [&](PRegs<real>& R, int i) {
+        // Software pipeline: the next particle of this thread is loaded while
+        // the current one is pushed.  Every lane issues the same loads and
+        // stores in every iteration (clamped load index, masked-off lanes
+        // storing into the spare slots), so the wait for the prefetched data
+        // does not also wait for this iteration's stores to complete.
+        int cell_n = 0;
+        real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
+             s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
+        auto load = [&](int i) {
             const uint32_t bi = (uint32_t)(start + i) * 4u;
             const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
-            R.cell = ldo(p.cell, bi);
+            cell_n = ldo(p.cell, bi);
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) R.o[a] = ldo(p.off[a], br);
+            for (int a = 0; a < DIM; ++a) o_n[a] = ldo(p.off[a], br);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                R.u[a] = ldo(p.u[a], br);
-                R.s[a] = ldo(p.s[a], br);
+                u_n[a] = ldo(p.u[a], br);
+                s_n[a] = ldo(p.s[a], br);
             }
-            R.w = ldo(p.w, br);
+            w_n = ldo(p.w, br);
         };
-        auto pass = [&](int base, const PRegs<real>& P) {
+        if (n > 0) load(min((int)threadIdx.x, n - 1));
+
+        for (int base = 0; base < n; base += kBlock) {
             const int i = base + threadIdx.x;
             const bool active = i < n;
-            const int cell0 = P.cell;
+            const int cell0 = cell_n;
             real o[3], u[3], s[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                o[a] = a < DIM ? P.o[a] : real(0);
-                u[a] = P.u[a];
-                s[a] = P.s[a];
+                o[a] = o_n[a];
+                u[a] = u_n[a];
+                s[a] = s_n[a];
             }
-            const real wgt = P.w;
+            const real wgt = w_n;
+            if (base + kBlock < n) load(min(i + kBlock, n - 1));
 
             bool leave = false;
             int newcell = cell0;
@@ -287,46 +300,7 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
             }
             const unsigned long long m = __ballot(leave);
             if (lane == 0) leavemask[(base >> 6) + wave] = m;
-        };
-        // three register sets in rotation (unrolled by three), so that no set
-        // is copied and the loads stay two passes ahead of their use
-        auto phase = [&](int base, const PRegs<real>& P, PRegs<real>& L) {
-            load(L, min(base + 2 * kBlock + (int)threadIdx.x, n - 1));
-            pass(base, P);
-        };
-        // The prologue issues the same sequence of memory operations as a
-        // pass (loads, then one store per array into the spare slots), so
-        // that the loop is entered with the memory counter in its steady
-        // state and the waits inside it can stay loose.  Load indices are
-        // clamped into the segment.  The loop has a single exit (whole
-        // triples of passes); the last one or two passes follow it.
-        uint32_t spare_i = dummy_i, spare_r = dummy_r;
-        asm volatile("" : "+v"(spare_i), "+v"(spare_r));   // keep these 32-bit offsets here
-        auto spare_stores = [&]() {
-            sto(p.cell, spare_i, 0);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) sto(p.off[a], spare_r, real(0));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                sto(p.u[a], spare_r, real(0));
-                sto(p.s[a], spare_r, real(0));
-            }
-        };
-        const int npass = (n + kBlock - 1) / kBlock;
-        if (npass > 0) {
-            load(S0, min((int)threadIdx.x, n - 1));
-            spare_stores();
-            load(S1, min((int)threadIdx.x + kBlock, n - 1));
-            spare_stores();
         }
-        int j = 0;
-        for (; j + 3 <= npass; j += 3) {
-            phase(j * kBlock, S0, S2);
-            phase((j + 1) * kBlock, S1, S0);
-            phase((j + 2) * kBlock, S2, S1);
-        }
-        if (j < npass) pass(j * kBlock, S0);
-        if (j + 1 < npass) pass((j + 1) * kBlock, S1);
         __syncthreads();
 
         // Leavers and compaction, from the per-chunk leaver ballots in shared
@@ -364,16 +338,16 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
             const int lbase = s_lbase;
             const int nn = n - L;
             // leavers among slots [0, x), 0 <= x <= n
-            auto lcount = [&](int x) {
+            auto leavers_below = [&](int x) {
                 const int c = x >> 6;
                 return lprefix[c] + __popcll(leavemask[c] & ((1ull << (x & 63)) - 1ull));
             };
-            const int pairs = lcount(nn);
+            const int pairs = leavers_below(nn);
             for (int r0 = 0; r0 == 0 || r0 < pairs; r0 += kPairCap) {
                 for (int q = threadIdx.x; q < L; q += kBlock) {
                     const int pos = nn + q;
                     if (!((leavemask[pos >> 6] >> (pos & 63)) & 1ull)) {
-                        const int rank = q - (lcount(pos) - pairs);
+                        const int rank = q - (leavers_below(pos) - pairs);
                         if (rank >= r0 && rank < r0 + kPairCap) srcpos[rank - r0] = pos;
                     }
                 }

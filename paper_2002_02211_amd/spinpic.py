@@ -255,10 +255,10 @@ def pic_energy(ctx, nspecies):
 
 
 def pic_stats(ctx):
-    out = (ctypes.c_int64 * 5)()
-    _check(load_library().pic_stats(ctx, out, 5), ctx)
+    out = (ctypes.c_int64 * 8)()
+    _check(load_library().pic_stats(ctx, out, 8), ctx)
     return {"steps": out[0], "moved": out[1], "overflow": out[2], "repacks": out[3],
-            "particles": out[4]}
+            "particles": out[4], "tile": (out[5], out[6], out[7])}
 
 
 def pic_timing(ctx, enable):

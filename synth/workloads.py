@@ -86,7 +86,7 @@ def _c2(**kw):
 
 
 def _c3(**kw):
-    s = _base("c3", 3, (512, 256, 256), (0.1, 0.1, 0.1), 500, 3, "fp32", (8, 8, 8))
+    s = _base("c3", 3, (512, 256, 256), (0.1, 0.1, 0.1), 500, 3, "fp32", (0, 0, 0))
     s["plasma"] = {"ppc": 2, "profile": "uniform", "n0": 0.005, "ramp_len": 0.0,
                    "noise": 0.01, "T_keV": 1.0, "s0": (1.0, 0.0, 0.0)}
     s["laser"] = {"a0": 20.0, "waist": 6 * LAMBDA, "duration": 10 * LAMBDA,
@@ -107,7 +107,7 @@ def _small2d(**kw):
 
 
 def _small3d(**kw):
-    s = _base("small3d", 3, (20, 12, 10), (0.1, 0.1, 0.1), 20, 12, "fp64", (8, 8, 8))
+    s = _base("small3d", 3, (20, 12, 10), (0.1, 0.1, 0.1), 20, 12, "fp64", (0, 0, 0))
     s["plasma"] = {"ppc": 2, "profile": "uniform", "n0": 0.05, "ramp_len": 0.0,
                    "noise": 0.02, "T_keV": 5.0, "s0": (1.0, 0.0, 0.0)}
     s["laser"] = {"a0": 3.0, "waist": 0.4 * LAMBDA, "duration": 0.8 * LAMBDA,

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Inputs are the seeded synthetic plasmas of ``synth`` (c1-like, with ragged
-16x16 tiles in 2D and 6^3 / 8^3 tiles in 3D).  FP64 runs must match the oracle
+16x16 tiles in 2D; in 3D the default 12x6x6 (FP32) and 6^3 (FP64) tiles and
+explicit 8^3 and 4^3 ones).  FP64 runs must match the oracle
 per particle (position in cells, momentum relative to max(|u|, u_thermal),
 spin) and per field cell to 1e-9 relative; FP32-mixed runs to the 1e-5 per
 particle bound (and 1e-3 on the polarization vector).
@@ -89,8 +90,9 @@ def test_fp64_parity_over_run(name, nsteps, every):
 
 
 @pytest.mark.parametrize("acc", [S.PIC_ACC_FP64, S.PIC_ACC_FP32])
-@pytest.mark.parametrize("name,nsteps", [("small2d", 40), ("small3d", 20)])
-def test_fp32_mixed_parity(name, nsteps, acc):
+@pytest.mark.parametrize("name,nsteps,tile", [("small2d", 40, None), ("small3d", 20, None),
+                                              ("small3d", 20, (8, 8, 8))])
+def test_fp32_mixed_parity(name, nsteps, tile, acc):
     """FP32 particles against the FP64 oracle.
 
     The polarization vector must agree to 1e-3.  Per particle the bound is
@@ -100,8 +102,8 @@ def test_fp32_mixed_parity(name, nsteps, acc):
     FP32 run may not exceed 3x its error at the median, 99th percentile and
     maximum.
     """
-    spec = synth.preset(name)
-    _say(name, "fp32 acc", acc, nsteps, "steps")
+    spec = synth.preset(name) if tile is None else synth.preset(name, tile=tile)
+    _say(name, "fp32 acc", acc, "tile", tile, nsteps, "steps")
     state = synth.make_state(spec)
     sim, ref = _pair(spec, precision="fp32", deposit_acc=acc, state=state)
     ideal = oracle.Sim(spec, state, store_fp32=True)
