@@ -141,6 +141,37 @@ int pic_polarization(pic_ctx* ctx, int32_t species, double ekin_min_mev,
  * step.  cap_doubles must hold popcount(mask)*cells values.  Waits. */
 int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles);
 
+/* Binned diagnostics (the energy spectra and polarization-versus-energy
+ * plots of the paper's section 3).  All sums in FP64 on the device; all wait
+ * for the stream.  Bins are equal over [lo, hi): a value v falls in bin
+ * floor((v - lo) / (hi - lo) * nbins), capped at nbins - 1, and values outside
+ * [lo, hi) are not counted.  Kinetic energy is mu*(sqrt(1 + u2) - 1)*0.51099895
+ * MeV with u2 = (ux*ux + uy*uy) + uz*uz, summed in that order. */
+#define PIC_MAX_SPECTRUM_BINS 1024
+
+/* Energy spectrum of one species (species = -1: all) in nbins bins over
+ * [emin, emax) MeV, 1 <= nbins <= PIC_MAX_SPECTRUM_BINS: count_out[b] number of
+ * macro-particles, weight_out[b] sum of their weights, spin_out[3b + k] sum of
+ * s_k, so that section 2 Eq. 4 for bin b is spin_out[3b + k] / count_out[b].
+ * The three host arrays hold nbins, nbins and 3*nbins doubles.  Errors:
+ * PIC_EINVAL for a bad species, nbins, range (need emin < emax, finite) or a
+ * NULL array. */
+int pic_spectrum(pic_ctx* ctx, int32_t species, double emin, double emax, int32_t nbins,
+                 double* count_out, double* weight_out, double* spin_out);
+
+/* Weighted position-momentum histogram of one species: position along axis
+ * (0 .. ndim-1, in c/omega0, as pic_particles reports it) in nx bins over
+ * [xmin, xmax), momentum mu*u_comp (comp 0 .. 2, in m_e c) in np bins over
+ * [pmin, pmax); out[ix*np + ip] receives the sum of w (nx*np doubles,
+ * nx*np <= 2^26).  Errors: PIC_EINVAL for bad arguments. */
+int pic_phase_space(pic_ctx* ctx, int32_t species, int32_t axis, double xmin, double xmax,
+                    int32_t nx, int32_t comp, double pmin, double pmax, int32_t np, double* out);
+
+/* Number density of one species on the nodes: the cloud-in-cell sum of w
+ * (the charge density of that species divided by Z), float64 [nz][ny][nx];
+ * cap_doubles must hold the cell count. */
+int pic_density(pic_ctx* ctx, int32_t species, double* out, size_t cap_doubles);
+
 /* Copy the particles of one species, sorted by id (the row index in the
  * initial state), as rows of PIC_PARTICLE_OUT_COLS float64 values.  cap_doubles
  * must hold count*11 values; *n_out receives the count.  Waits. */

@@ -9,5 +9,6 @@ from .pic import (  # noqa: F401
     Grid, Sim, interpolate, gather, cross_matrix, midpoint_rotate, boris,
     tbmt_omega, spin_precess, move, wrap, shape_pair, deposit,
     charge_density, curl_E, curl_B, div_E, yee_step, kinetic_energy_mev,
-    polarization, E_STAGGER, B_STAGGER,
+    polarization, E_STAGGER, B_STAGGER, kinetic_energy_binned, bin_index,
+    spectrum, phase_space,
 )

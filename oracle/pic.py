@@ -23,7 +23,10 @@ positions x^n, momenta u^(n-1/2), spins s^(n-1/2)):
 
 Diagnostics: the polarization of section 2 Eq. 4 (mean spin over an ensemble
 selected by species and kinetic-energy window), energies, the charge density
-and the discrete div E - rho residual.
+and the discrete div E - rho residual; binned: the energy spectrum with the
+Eq. 4 polarization of every energy bin (the spectra and polarization-versus-
+energy plots of section 3), weighted position-momentum histograms and the
+number density of a species.
 
 Units are normalized laser units (time 1/omega0, length c/omega0, fields
 m_e c omega0/e, densities n_c).  In them q/(mc) of Eq. 2 becomes r = Z/mu and
@@ -339,6 +342,49 @@ def polarization(s, selected):
     return s[selected].sum(axis=0) / N, N
 
 
+# ---------------------------------------------------------------- binned diagnostics
+
+def kinetic_energy_binned(u, mu):
+    """mu (gamma - 1) m_e c^2 in MeV with |u|^2 summed as (ux^2 + uy^2) + uz^2,
+    the order the binned diagnostics fix so that bin decisions are
+    reproducible bit for bit."""
+    u2 = (u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1]) + u[:, 2] * u[:, 2]
+    return mu * (np.sqrt(1.0 + u2) - 1.0) * ME_C2_MEV
+
+
+def bin_index(v, lo, hi, nbins):
+    """Equal bins over [lo, hi): index floor((v - lo) / (hi - lo) * nbins),
+    capped at nbins - 1; -1 for values outside [lo, hi)."""
+    inside = (v >= lo) & (v < hi)
+    b = np.floor((v - lo) / (hi - lo) * nbins)
+    b = np.minimum(b, nbins - 1)
+    return np.where(inside, b, -1).astype(np.int64)
+
+
+def spectrum(u, s, w, mu, emin, emax, nbins):
+    """Energy spectrum with the polarization of section 2 Eq. 4 per bin: for
+    nbins equal bins of kinetic energy over [emin, emax) MeV, the number of
+    macro-particles, the sum of their weights and the sum of their spin
+    vectors (so the polarization of bin b is spin[b] / count[b])."""
+    b = bin_index(kinetic_energy_binned(u, mu), emin, emax, nbins)
+    keep = b >= 0
+    count = np.bincount(b[keep], minlength=nbins).astype(np.float64)
+    weight = np.bincount(b[keep], weights=w[keep], minlength=nbins)
+    spin = np.stack([np.bincount(b[keep], weights=s[keep, k], minlength=nbins)
+                     for k in range(3)], axis=1)
+    return count, weight, spin
+
+
+def phase_space(x, p, w, xmin, xmax, nx, pmin, pmax, np_):
+    """Weighted 2D histogram over (position, momentum): nx by np_ equal bins
+    over [xmin, xmax) x [pmin, pmax); out[ix, ip] = sum of w."""
+    bx = bin_index(x, xmin, xmax, nx)
+    bp = bin_index(p, pmin, pmax, np_)
+    keep = (bx >= 0) & (bp >= 0)
+    flat = bx[keep] * np_ + bp[keep]
+    return np.bincount(flat, weights=w[keep], minlength=nx * np_).reshape(nx, np_)
+
+
 # ---------------------------------------------------------------- driver
 
 class Sim:
@@ -452,6 +498,29 @@ class Sim:
         masks = self.select(species, emin, emax)
         s = np.concatenate(self.s, axis=0)
         return polarization(s, np.concatenate(masks))
+
+    def spectrum(self, species, emin, emax, nbins):
+        """Binned energy spectrum of one species (-1: all), see spectrum()."""
+        out = [np.zeros(nbins), np.zeros(nbins), np.zeros((nbins, 3))]
+        for k, (Z, mu, a) in enumerate(self.species):
+            if species not in (-1, k):
+                continue
+            part = spectrum(self.u[k], self.s[k], self.w[k], mu, emin, emax, nbins)
+            for q in range(3):
+                out[q] += part[q]
+        return tuple(out)
+
+    def phase_space(self, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_):
+        """Weighted histogram of position x_axis (c/omega0) against mu u_comp
+        (m_e c) for one species."""
+        Z, mu, a = self.species[species]
+        x = self.xi[species][:, axis] * self.grid.d[axis]
+        return phase_space(x, mu * self.u[species][:, comp], self.w[species],
+                           xmin, xmax, nx, pmin, pmax, np_)
+
+    def density(self, species):
+        """Number density of one species on the nodes (CIC of w)."""
+        return charge_density(self.xi[species], self.w[species], self.grid)
 
     def fields(self):
         """(10, nz, ny, nx): Ex Ey Ez Bx By Bz Jx Jy Jz rho."""

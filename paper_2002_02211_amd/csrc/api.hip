@@ -163,6 +163,11 @@ public:
     virtual Status polarization(int species, double emin, double emax, double P[3], int64_t* N) = 0;
     virtual Status fields(uint32_t mask, double* out, size_t cap) = 0;
     virtual Status particles(int species, double* out, size_t cap, int64_t* n) = 0;
+    virtual Status spectrum(int species, double emin, double emax, int nbins, double* count,
+                            double* weight, double* spin) = 0;
+    virtual Status phase_space(int species, int axis, double xmin, double xmax, int nx, int comp,
+                               double pmin, double pmax, int np, double* out) = 0;
+    virtual Status density(int species, double* out, size_t cap) = 0;
     virtual Status energy(double* out, int cap) = 0;
     virtual Status stats(int64_t* out, int cap) = 0;
     virtual Status timing(int enable) = 0;
@@ -186,6 +191,11 @@ public:
     Status polarization(int species, double emin, double emax, double P[3], int64_t* N) override;
     Status fields(uint32_t mask, double* out, size_t cap) override;
     Status particles(int species, double* out, size_t cap, int64_t* n) override;
+    Status spectrum(int species, double emin, double emax, int nbins, double* count, double* weight,
+                    double* spin) override;
+    Status phase_space(int species, int axis, double xmin, double xmax, int nx, int comp, double pmin,
+                       double pmax, int np, double* out) override;
+    Status density(int species, double* out, size_t cap) override;
     Status energy(double* out, int cap) override;
     Status stats(int64_t* out, int cap) override;
     Status timing(int enable) override;
@@ -749,6 +759,100 @@ Status Engine<real, DIM>::polarization(int species, double emin, double emax, do
 }
 
 template <typename real, int DIM>
+Status Engine<real, DIM>::spectrum(int species, double emin, double emax, int nbins, double* count,
+                                   double* weight, double* spin) {
+    if (species < -1 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (nbins < 1 || nbins > PIC_MAX_SPECTRUM_BINS)
+        return fail(PIC_EINVAL, "nbins = %d outside 1..%d", nbins, PIC_MAX_SPECTRUM_BINS);
+    if (!std::isfinite(emin) || !std::isfinite(emax) || !(emin < emax))
+        return fail(PIC_EINVAL, "energy range must be finite with emin < emax");
+    if (!count || !weight || !spin) return fail(PIC_EINVAL, "output arrays must not be NULL");
+    BinArgs ba{};
+    ba.mode = BIN_SPECTRUM;
+    ba.species = species;
+    ba.lo = emin;
+    ba.hi = emax;
+    ba.nbins = nbins;
+    for (int sp = 0; sp < kMaxSpecies; ++sp) ba.mu[sp] = sp < g_.nsp ? R_.cfg.sp[sp].mu : 1.0;
+    const size_t nh = (size_t)5 * nbins;
+    double* d = (double*)dalloc(nh * sizeof(double));
+    if (!d) return fail(PIC_ENOMEM, "spectrum buffer allocation failed");
+    std::vector<double> h(nh);
+    hipError_t e = hipMemsetAsync(d, 0, nh * sizeof(double), stream_);
+    if (e == hipSuccess) e = launch_bin_particles<real, DIM>(g_, p_, seg_, st_, ctr_, ba, d, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, nh * sizeof(double), hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    dfree(d);
+    if (e != hipSuccess) return fail(PIC_EHIP, "spectrum: %s", hipGetErrorString(e));
+    for (int b = 0; b < nbins; ++b) {
+        count[b] = h[b];
+        weight[b] = h[nbins + b];
+    }
+    for (int q = 0; q < 3 * nbins; ++q) spin[q] = h[2 * (size_t)nbins + q];
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::phase_space(int species, int axis, double xmin, double xmax, int nx, int comp,
+                                      double pmin, double pmax, int np, double* out) {
+    if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (axis < 0 || axis >= DIM) return fail(PIC_EINVAL, "axis %d outside 0..%d", axis, DIM - 1);
+    if (comp < 0 || comp > 2) return fail(PIC_EINVAL, "momentum component %d outside 0..2", comp);
+    if (nx < 1 || np < 1 || (long long)nx * np > (1LL << 26))
+        return fail(PIC_EINVAL, "bins %d x %d: need >= 1 each and at most 2^26 in all", nx, np);
+    if (!std::isfinite(xmin) || !std::isfinite(xmax) || !(xmin < xmax) || !std::isfinite(pmin) ||
+        !std::isfinite(pmax) || !(pmin < pmax))
+        return fail(PIC_EINVAL, "ranges must be finite with min < max");
+    if (!out) return fail(PIC_EINVAL, "out must not be NULL");
+    BinArgs ba{};
+    ba.mode = BIN_PHASE;
+    ba.species = species;
+    ba.lo = xmin;
+    ba.hi = xmax;
+    ba.nbins = nx;
+    ba.axis = axis;
+    ba.comp = comp;
+    ba.plo = pmin;
+    ba.phi = pmax;
+    ba.np = np;
+    for (int a = 0; a < 3; ++a) ba.d[a] = d_[a];
+    for (int sp = 0; sp < kMaxSpecies; ++sp) ba.mu[sp] = sp < g_.nsp ? R_.cfg.sp[sp].mu : 1.0;
+    const size_t nh = (size_t)nx * np;
+    double* d = (double*)dalloc(nh * sizeof(double));
+    if (!d) return fail(PIC_ENOMEM, "phase-space buffer allocation failed");
+    hipError_t e = hipMemsetAsync(d, 0, nh * sizeof(double), stream_);
+    if (e == hipSuccess) e = launch_bin_particles<real, DIM>(g_, p_, seg_, st_, ctr_, ba, d, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, nh * sizeof(double), hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    dfree(d);
+    if (e != hipSuccess) return fail(PIC_EHIP, "phase space: %s", hipGetErrorString(e));
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::density(int species, double* out, size_t cap) {
+    if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (!out) return fail(PIC_EINVAL, "out must not be NULL");
+    if (cap < (size_t)g_.ncells) return fail(PIC_EINVAL, "cap too small: need %lld doubles", g_.ncells);
+    ReduceArgs ra{};
+    ra.species = species;
+    for (int sp = 0; sp < kMaxSpecies; ++sp) {
+        ra.mu[sp] = sp < g_.nsp ? R_.cfg.sp[sp].mu : 1.0;
+        ra.Z[sp] = sp == species ? 1.0 : 0.0;
+    }
+    double* d = (double*)dalloc((size_t)g_.ncells * sizeof(double));
+    if (!d) return fail(PIC_ENOMEM, "density buffer allocation failed");
+    hipError_t e = hipMemsetAsync(d, 0, (size_t)g_.ncells * sizeof(double), stream_);
+    if (e == hipSuccess)
+        e = launch_reduce_particles<real, DIM>(RED_RHO, g_, p_, seg_, st_, ctr_, ra, acc_, d, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, (size_t)g_.ncells * sizeof(double), hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    dfree(d);
+    if (e != hipSuccess) return fail(PIC_EHIP, "density: %s", hipGetErrorString(e));
+    return Status{};
+}
+
+template <typename real, int DIM>
 Status Engine<real, DIM>::fields(uint32_t mask, double* out, size_t cap) {
     if (mask & ~0x3FFu) return fail(PIC_EINVAL, "unknown field mask bits 0x%x", mask);
     const size_t N = (size_t)g_.ncells;
@@ -1019,6 +1123,23 @@ int pic_polarization(pic_ctx* ctx, int32_t species, double emin, double emax, do
 int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles) {
     CTX_CHECK(ctx);
     return finish(ctx, ctx->eng->fields(mask, host_out, cap_doubles));
+}
+
+int pic_spectrum(pic_ctx* ctx, int32_t species, double emin, double emax, int32_t nbins,
+                 double* count_out, double* weight_out, double* spin_out) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->spectrum(species, emin, emax, nbins, count_out, weight_out, spin_out));
+}
+
+int pic_phase_space(pic_ctx* ctx, int32_t species, int32_t axis, double xmin, double xmax,
+                    int32_t nx, int32_t comp, double pmin, double pmax, int32_t np, double* out) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->phase_space(species, axis, xmin, xmax, nx, comp, pmin, pmax, np, out));
+}
+
+int pic_density(pic_ctx* ctx, int32_t species, double* out, size_t cap_doubles) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->density(species, out, cap_doubles));
 }
 
 int pic_particles(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles, int64_t* n_out) {

@@ -133,6 +133,7 @@ __device__ inline void reduce_one(int mode, const PArrays<real>& p, long long i,
     } else if (mode == RED_KINETIC) {
         v[sp] += ra.mu[sp] * (gamma - 1.0) * (double)p.w[i];
     } else {
+        if (ra.species >= 0 && sp != ra.species) return;
         int c[3];
         unpack_cell<DIM>(p.cell[i], c[0], c[1], c[2]);
         const double q = ra.Z[sp] * (double)p.w[i];
@@ -173,6 +174,89 @@ k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st
             reduce_one<real, DIM>(mode, st, i, st.sp[i], g, ra, v, rho);
     }
     if (mode != RED_RHO) block_sum_add<4>(v, acc);
+}
+
+// Bin of v among n equal bins over [lo, hi), or -1 outside.  The energy and
+// bin arithmetic is written out without contraction into fused multiply-adds,
+// so that bin decisions are reproducible from the particle values alone.
+__device__ inline int bin_of(double v, double lo, double hi, int n) {
+#pragma clang fp contract(off)
+    if (!(v >= lo && v < hi)) return -1;
+    const double b = floor((v - lo) / (hi - lo) * (double)n);
+    return b >= (double)(n - 1) ? n - 1 : (int)b;
+}
+
+__device__ inline double kinetic_mev(double ux, double uy, double uz, double mu) {
+#pragma clang fp contract(off)
+    const double u2 = (ux * ux + uy * uy) + uz * uz;
+    return mu * (sqrt(1.0 + u2) - 1.0) * kMeC2MeV;
+}
+
+template <typename real, int DIM>
+__device__ inline void bin_one(const PArrays<real>& p, long long i, int sp, const BinArgs& ba,
+                               double* hist, double* out) {
+    if (ba.mode == BIN_SPECTRUM) {
+        const int b = bin_of(kinetic_mev((double)p.u[0][i], (double)p.u[1][i], (double)p.u[2][i], ba.mu[sp]),
+                             ba.lo, ba.hi, ba.nbins);
+        if (b < 0) return;
+        atomicAdd(hist + b, 1.0);
+        atomicAdd(hist + ba.nbins + b, (double)p.w[i]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(hist + 2 * ba.nbins + 3 * b + k, (double)p.s[k][i]);
+    } else {
+        int c[3];
+        unpack_cell<DIM>(p.cell[i], c[0], c[1], c[2]);
+        double x;
+        {
+#pragma clang fp contract(off)
+            x = ((double)c[ba.axis] + (double)p.off[ba.axis][i]) * ba.d[ba.axis];
+        }
+        const int bx = bin_of(x, ba.lo, ba.hi, ba.nbins);
+        if (bx < 0) return;
+        double pm;
+        {
+#pragma clang fp contract(off)
+            pm = ba.mu[sp] * (double)p.u[ba.comp][i];
+        }
+        const int bp = bin_of(pm, ba.plo, ba.phi, ba.np);
+        if (bp < 0) return;
+        atomicAdd(out + (long long)bx * ba.np + bp, (double)p.w[i]);
+    }
+}
+
+// Workgroups stride over the tile segments, then over the overflow store.
+// The spectrum is summed in shared memory per workgroup and added to out
+// once; the phase-space histogram goes to out directly.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_bin_particles(Geom g, PArrays<real> p, Segs seg, PArrays<real> st, const int32_t* __restrict__ ctr,
+                BinArgs ba, double* out) {
+    extern __shared__ double hist[];
+    const bool spectrum = ba.mode == BIN_SPECTRUM;
+    const int nh = 5 * ba.nbins;
+    if (spectrum) {
+        for (int b = threadIdx.x; b < nh; b += kBlock) hist[b] = 0.0;
+        __syncthreads();
+    }
+    const int nseg = g.ntiles * g.nsp;
+    for (int sid = blockIdx.x; sid < nseg; sid += gridDim.x) {
+        const int sp = sid % g.nsp;
+        if (ba.species >= 0 && sp != ba.species) continue;
+        const long long start = seg.start[sid];
+        const int n = seg.count[sid];
+        for (int i = threadIdx.x; i < n; i += kBlock) bin_one<real, DIM>(p, start + i, sp, ba, hist, out);
+    }
+    const int nst = ctr[CTR_STASH];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nst; i += gridDim.x * kBlock) {
+        const int sp = st.sp[i];
+        if (ba.species >= 0 && sp != ba.species) continue;
+        bin_one<real, DIM>(st, i, sp, ba, hist, out);
+    }
+    if (spectrum) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < nh; b += kBlock)
+            if (hist[b] != 0.0) atomicAdd(out + b, hist[b]);
+    }
 }
 
 template <typename real>
@@ -272,6 +356,18 @@ hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>&
     return hipGetLastError();
 }
 
+template <typename real, int DIM>
+hipError_t launch_bin_particles(const Geom& g, const PArrays<real>& p, const Segs& seg,
+                                const PArrays<real>& st, const int32_t* ctr, const BinArgs& ba,
+                                double* out, hipStream_t stream) {
+    const int nseg = g.ntiles * g.nsp;
+    const int blocks = nseg < 1024 ? (nseg > 0 ? nseg : 1) : 1024;
+    const size_t lds = ba.mode == BIN_SPECTRUM ? (size_t)5 * ba.nbins * sizeof(double) : 0;
+    hipLaunchKernelGGL((k_bin_particles<real, DIM>), dim3(blocks), dim3(kBlock), lds, stream, g, p,
+                       seg, st, ctr, ba, out);
+    return hipGetLastError();
+}
+
 template <typename real>
 hipError_t launch_field_energy(const Geom& g, const Fields<real>& f, double* acc,
                                hipStream_t stream) {
@@ -313,7 +409,9 @@ hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStr
 #define SPINPIC_INST_PART(real, DIM)                                                           \
     template hipError_t launch_reduce_particles<real, DIM>(int, const Geom&,                  \
         const PArrays<real>&, const Segs&, const PArrays<real>&, const int32_t*,               \
-        const ReduceArgs&, double*, double*, hipStream_t);
+        const ReduceArgs&, double*, double*, hipStream_t);                                      \
+    template hipError_t launch_bin_particles<real, DIM>(const Geom&, const PArrays<real>&,     \
+        const Segs&, const PArrays<real>&, const int32_t*, const BinArgs&, double*, hipStream_t);
 
 SPINPIC_INST_GRID(2)
 SPINPIC_INST_GRID(3)

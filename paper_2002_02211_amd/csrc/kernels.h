@@ -42,7 +42,8 @@ hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real
 // FP64 reductions.  acc receives sums by atomic adds and must be zeroed first.
 //   polarization: acc[0..2] += s, acc[3] += 1 over the selected particles.
 //   kinetic:      acc[sp] += mu (gamma - 1) w.
-//   rho:          rho (ncells doubles) += CIC charge Z w on the nodes.
+//   rho:          rho (ncells doubles) += CIC charge Z w on the nodes (one
+//                 species, or all with species = -1).
 struct ReduceArgs {
     int species;            // -1 = all
     double emin, emax;      // MeV window [emin, emax)
@@ -56,6 +57,29 @@ hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>&
                                    const ReduceArgs& ra, double* acc, double* rho,
                                    hipStream_t stream);
 enum { RED_POLARIZATION = 0, RED_KINETIC = 1, RED_RHO = 2 };
+
+// Binned diagnostics over all particles (tiles and overflow store).
+//   spectrum: out[b] += 1, out[nbins + b] += w, out[2 nbins + 3 b + k] += s_k
+//             for kinetic energy in bin b of [lo, hi) (species -1: all);
+//   phase:    out[ix * np + ip] += w for position x_axis in bin ix of
+//             [lo, hi) and mu u_comp in bin ip of [plo, phi) (one species).
+struct BinArgs {
+    int mode;
+    int species;
+    double lo, hi;
+    int nbins;
+    int axis, comp;
+    double plo, phi;
+    int np;
+    double d[3];
+    double mu[kMaxSpecies];
+};
+enum { BIN_SPECTRUM = 0, BIN_PHASE = 1 };
+
+template <typename real, int DIM>
+hipError_t launch_bin_particles(const Geom& g, const PArrays<real>& p, const Segs& seg,
+                                const PArrays<real>& st, const int32_t* ctr, const BinArgs& ba,
+                                double* out, hipStream_t stream);
 
 // Field energy: acc[0] += sum (E^2 + B^2) / 2 over the cells.
 template <typename real>

@@ -26,8 +26,8 @@ PIC_FLAG_TEST_PARTICLE = 1
 MAX_SPECIES = 4
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
-            "pic_energy", "pic_stats", "pic_timing", "pic_timing_read", "pic_last_error",
-            "pic_free")
+            "pic_spectrum", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
+            "pic_timing", "pic_timing_read", "pic_last_error", "pic_free")
 
 _ERR_NAMES = {PIC_EINVAL: "PIC_EINVAL", PIC_ECFL: "PIC_ECFL", PIC_EHIP: "PIC_EHIP",
               PIC_ECAPACITY: "PIC_ECAPACITY", PIC_ENONFINITE: "PIC_ENONFINITE",
@@ -93,6 +93,13 @@ def load_library(path=LIB_PATH):
     lib.pic_fields.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]
     lib.pic_particles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)]
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.pic_spectrum.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                 D, D, D]
+    lib.pic_phase_space.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, D]
+    lib.pic_density.argtypes = [P, ctypes.c_int32, D, ctypes.c_size_t]
     lib.pic_energy.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     lib.pic_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     lib.pic_timing.argtypes = [P, ctypes.c_int32]
@@ -248,6 +255,30 @@ def pic_particles(ctx, species, count):
     return out[: n.value]
 
 
+def pic_spectrum(ctx, species, emin, emax, nbins):
+    """(count, weight, spin) per kinetic-energy bin; spin has shape (nbins, 3)."""
+    count = np.zeros(int(nbins))
+    weight = np.zeros(int(nbins))
+    spin = np.zeros((int(nbins), 3))
+    _check(load_library().pic_spectrum(ctx, int(species), float(emin), float(emax), int(nbins),
+                                       _dptr(count), _dptr(weight), _dptr(spin)), ctx)
+    return count, weight, spin
+
+
+def pic_phase_space(ctx, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_):
+    out = np.zeros((int(nx), int(np_)))
+    _check(load_library().pic_phase_space(ctx, int(species), int(axis), float(xmin), float(xmax),
+                                          int(nx), int(comp), float(pmin), float(pmax), int(np_),
+                                          _dptr(out)), ctx)
+    return out
+
+
+def pic_density(ctx, species, cells):
+    out = np.empty(int(cells))
+    _check(load_library().pic_density(ctx, int(species), _dptr(out), out.size), ctx)
+    return out
+
+
 def pic_energy(ctx, nspecies):
     out = np.empty(nspecies + 2)
     _check(load_library().pic_energy(ctx, _dptr(out), out.size), ctx)
@@ -312,6 +343,15 @@ class Simulation:
 
     def energy(self):
         return pic_energy(self.ctx, self.nspecies)
+
+    def spectrum(self, species, emin, emax, nbins):
+        return pic_spectrum(self.ctx, species, emin, emax, nbins)
+
+    def phase_space(self, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_):
+        return pic_phase_space(self.ctx, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_)
+
+    def density(self, species):
+        return pic_density(self.ctx, species, self.cells).reshape(self.shape)
 
     def stats(self):
         return pic_stats(self.ctx)

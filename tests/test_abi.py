@@ -154,6 +154,9 @@ def test_T16_calls_on_null_context(lib):
     assert lib.pic_fields(None, 1, None, 0) == S.PIC_ESTATE
     assert lib.pic_energy(None, None, 0) == S.PIC_ESTATE
     assert lib.pic_stats(None, None, 0) == S.PIC_ESTATE
+    assert lib.pic_spectrum(None, 0, 0.0, 1.0, 4, None, None, None) == S.PIC_ESTATE
+    assert lib.pic_phase_space(None, 0, 0, 0.0, 1.0, 4, 0, -1.0, 1.0, 4, None) == S.PIC_ESTATE
+    assert lib.pic_density(None, 0, None, 0) == S.PIC_ESTATE
     lib.pic_free(None)
 
 
