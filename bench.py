@@ -46,7 +46,20 @@ WORKLOAD_TEXT = {
           "spins +y",
     "c3": "3D3V PIC, 512x256x256 cells of 0.1 lambda, e+p at 2 per cell each (134,217,728 particles), "
           "0.005 n_c with 1% noise, 1 keV, CP a0=20 waist 6 lambda, spins +x",
+    "c4": "differentiable spin tracking: 2^20 protons, analytic wake E0=0.1 kp=0.1, dt=0.5, 4000 steps, "
+          "states kept every 100; final polarization and its gradient w.r.t. E0, kp and the initial phase space",
 }
+
+# Algorithmic FP32 operations per particle-step of the tracking kernels
+# (add, multiply, divide, square root: 1 each, fused multiply-add: 2; sine
+# and cosine of one angle: 1 each), counted from the step's formula: fields
+# 15, Boris 55, Thomas-BMT rotation 83, move 22, state update 9; the backward
+# pass recomputes the step twice (once for its segment, once inside the
+# adjoint) and adds the reverse sweep (380).
+TRACK_FLOP_FORWARD = 184
+TRACK_FLOP_BACKWARD = 184 + 184 + 380
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
 def algorithmic_bytes(ndim, precision, npart, ncells):
@@ -175,6 +188,98 @@ def cpu_baseline(spec, state, sample_per_species):
                       % (n, sample_per_species, spec["name"], cpu_model(), dt)}
 
 
+def time_diagnostics(sim, spec, npart, precision, reps=5):
+    """Wall time per call of the binned diagnostics (kernel, clearing and
+    copy-back of the bins, synchronization) and the particle bytes each
+    reads: cell, offsets, u, s and w for the spectrum and the phase space (u
+    and w, the cell, one offset), cell, offsets and w for the density."""
+    import torch
+    r = 8 if precision == "fp64" else 4
+    nd = spec["ndim"]
+    L = spec["n"][0] * spec["d"][0]
+    calls = {
+        "spectrum_1024_bins": (lambda: sim.spectrum(-1, 0.0, 10.0, 1024), 7 * r),
+        "phase_space_x_px_512x128": (lambda: sim.phase_space(0, 0, 0.0, L, 512, 0, -5.0, 5.0, 128), 4 + r + r + r),
+        "density_electrons": (lambda: sim.density(0), 4 + nd * r + r),
+    }
+    out = {}
+    for name, (f, bpp) in calls.items():
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": dt * 1e3, "particles_per_s": npart / dt,
+                     "particle_bytes_GBps": npart * bpp / dt / 1e9}
+    return out
+
+
+def bench_tracking(args):
+    """One forward + backward of the c4 beam per step (the gradient of the
+    final polarization); prints one JSON line."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2002_02211_amd import spinpic as S
+    spec = synth.tracking_preset("c4")
+    precision = args.precision or spec["precision"]
+    x, u, s = synth.make_beam(spec)
+    sp = spec["species"]
+    tr = S.Tracker(spec["n"], Z=sp["Z"], mu=sp["mu"], a=sp["a"], dt=spec["dt"], nsteps=spec["nsteps"],
+                   checkpoint=spec["checkpoint"], precision=precision)
+    c = np.array([0.0, 0.0, 1.0])
+    for _ in range(args.warmup):
+        tr.forward(spec["E0"], spec["kp"], x, u, s)
+        tr.backward(c)
+    fwd, bwd = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P = tr.forward(spec["E0"], spec["kp"], x, u, s)
+        gth = tr.backward(c)[0]
+        t = tr.timing()
+        fwd.append(t["forward_ms"])
+        bwd.append(t["backward_ms"])
+    elapsed = time.perf_counter() - t0
+    tr.close()
+    n, ns = spec["n"], spec["nsteps"]
+    f_ms, b_ms = float(np.mean(fwd)), float(np.mean(bwd))
+    flops = n * ns * (TRACK_FLOP_FORWARD + TRACK_FLOP_BACKWARD)
+    peak = FP32_VECTOR_PEAK_TFLOPS if precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    achieved = flops / ((f_ms + b_ms) * 1e-3) / 1e12
+    result = {
+        "metric": "differentiable spin-tracking particle-steps/sec (forward + adjoint)",
+        "value": n * ns / ((f_ms + b_ms) * 1e-3), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "c4: " + WORKLOAD_TEXT["c4"], "particles": n, "track_steps": ns,
+                   "checkpoint": spec["checkpoint"],
+                   "precision": "FP32 trajectory and adjoint, FP64 sums" if precision == "fp32" else "FP64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_track_forward + k_track_backward",
+                     "flop_per_particle_step": TRACK_FLOP_FORWARD + TRACK_FLOP_BACKWARD,
+                     "forward_ms": f_ms, "backward_ms": b_ms},
+        "result": {"P": list(P), "dJ_dE0": gth[0], "dJ_dkp": gth[1]},
+    }
+    if not args.no_cpu_baseline:
+        import warnings
+        import oracle
+        warnings.simplefilter("ignore")
+        m, steps = 512, 4000
+        t0 = time.perf_counter()
+        oracle.per_particle_complex_step(x[:m], u[:m], s[:m], spec["E0"], spec["kp"], spec["dt"], steps,
+                                         sp["Z"], sp["mu"], sp["a"], c)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": m * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d particles x %d steps of the c4 beam, final state and complex-step gradient "
+                      "(11 complex runs), FP64 NumPy, one thread of %s, %.1f s" % (m, steps, cpu_model(), dt)}
+    print(json.dumps(result), flush=True)
+
+
 def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None):
     """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
     import torch
@@ -203,13 +308,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT),
+                    help="c1-c3: PIC steps; c4: differentiable tracking (forward + adjoint per step)")
     ap.add_argument("--precision", default=None, choices=("fp32", "fp64"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
                     help="precision of the per-tile shared-memory current sums (FP32 path)")
     ap.add_argument("--tile", default=None,
                     help="tile shape in cells, e.g. 16,16 or 8,8,6 (default: the library's choice)")
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="also time the binned diagnostics (spectrum, phase space, density)")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 run of the same workload (FP32 runs only)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -240,6 +348,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     S.load_library()
+    if args.workload == "c4":
+        if args.steps == 100 and args.warmup == 10:
+            args.steps, args.warmup = 5, 1
+        bench_tracking(args)
+        return
 
     spec = synth.preset(args.workload)
     precision = args.precision or spec["precision"]
@@ -300,6 +413,8 @@ def main():
                      "push_pushes_per_s": npart / avg_push_s},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
     }
+    if args.diagnostics:
+        result["diagnostics"] = time_diagnostics(sim, spec, npart, precision)
     sim.close()
     del sim
     torch.cuda.synchronize()

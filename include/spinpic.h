@@ -207,6 +207,67 @@ const char* pic_last_error(const pic_ctx* ctx);
  * with) after waiting for its stream.  NULL is ignored. */
 void pic_free(pic_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Differentiable test-particle spin tracking.
+ *
+ * n independent particles of one species cross an analytic linear wake moving
+ * at c along z; each step is the PIC step's Boris push and Thomas-BMT spin
+ * rotation (section 2 Eq. 1-3) with the fields evaluated at the particle,
+ * xi = z - t, S = sin(kp xi), C = cos(kp xi):
+ *     E = (E0 kp x S / 2, E0 kp y S / 2, E0 C),  B = (-E0 kp y S / 4, E0 kp x S / 4, 0)
+ * (E_z = E0 cos, radial E_r = E0 kp r / 2 sin, azimuthal B_phi = E_r / 2).
+ * Positions sit at t = n dt, momenta u = gamma beta and spins half a step
+ * earlier.  The forward pass returns P, the polarization of section 2 Eq. 4
+ * over all n particles after the last step; the backward pass returns the
+ * gradient of J = c . P with respect to E0, kp and every initial position,
+ * momentum and spin, by the adjoint of the discrete map (not of the ODE),
+ * recomputing K-step segments from states kept every K steps.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double Z, mu, a;       /* species: charge / e, mass / m_e, anomaly */
+    double dt;             /* time step (1/omega0), > 0 */
+    int32_t nsteps;        /* steps of a run, >= 0 */
+    int32_t checkpoint;    /* K: the state is kept every K steps, 1 <= K */
+    int32_t precision;     /* PIC_FP64, or PIC_FP32_MIXED: trajectory and adjoint
+                              in FP32, sums over particles in FP64 */
+} pic_track_config;
+
+typedef struct pic_track pic_track;
+
+/* Allocate the device buffers for n >= 1 particles (states, ceil(nsteps/K)
+ * checkpoints and K scratch states, 9 values each per particle).  alloc and
+ * hip_stream as for pic_init.  Errors: PIC_EINVAL, PIC_ENOMEM, PIC_EHIP. */
+int pic_track_create(const pic_track_config* cfg, int64_t n, const pic_allocator* alloc,
+                     void* hip_stream, pic_track** out);
+
+/* Run the trajectories for field parameters (E0, kp) from x0, u0, s0 (host,
+ * n rows of 3 float64 each, row-major).  P_out[3] receives the final
+ * polarization; x_out, u_out, s_out (host, n x 3, each may be NULL) the final
+ * state.  Keeps the checkpoints for pic_track_backward.  Waits.  Errors:
+ * PIC_EINVAL (NULL input, non-finite value), PIC_EHIP. */
+int pic_track_forward(pic_track* tr, double E0, double kp, const double* x0, const double* u0,
+                      const double* s0, double P_out[3], double* x_out, double* u_out,
+                      double* s_out);
+
+/* Gradient of J = c . P for the last forward run: grad_theta[0] = dJ/dE0,
+ * grad_theta[1] = dJ/dkp; grad_x0, grad_u0, grad_s0 (host, n x 3, each may be
+ * NULL) dJ/d(initial state); grad_theta_each (host, n x 2, may be NULL) each
+ * particle's share of the two parameter derivatives.  Waits.  Errors:
+ * PIC_ESTATE without a forward run, PIC_EINVAL, PIC_EHIP. */
+int pic_track_backward(pic_track* tr, const double c[3], double grad_theta[2], double* grad_x0,
+                       double* grad_u0, double* grad_s0, double* grad_theta_each);
+
+/* Kernel times of the last forward and backward runs in ms (HIP events on
+ * the handle's stream): ms_out[0] forward, ms_out[1] backward. */
+int pic_track_timing(pic_track* tr, double ms_out[2]);
+
+/* Reason for the last failure on tr, or of the last failed pic_track_create
+ * on this thread when tr is NULL. */
+const char* pic_track_last_error(const pic_track* tr);
+
+/* Release the handle and its device buffers.  NULL is ignored. */
+void pic_track_free(pic_track* tr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,3 +12,7 @@ from .pic import (  # noqa: F401
     polarization, E_STAGGER, B_STAGGER, kinetic_energy_binned, bin_index,
     spectrum, phase_space,
 )
+from .tracking import (  # noqa: F401
+    wake_fields, tracking_step, tracking_forward, objective, gradient_complex_step,
+    per_particle_complex_step,
+)

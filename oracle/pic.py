@@ -99,7 +99,7 @@ def gather(E, B, xi, grid):
 
 def cross_matrix(w):
     """Batched matrix K with K @ x = w x x."""
-    K = np.zeros(w.shape[:-1] + (3, 3))
+    K = np.zeros(w.shape[:-1] + (3, 3), dtype=np.result_type(w, np.float64))
     K[..., 0, 1] = -w[..., 2]
     K[..., 0, 2] = w[..., 1]
     K[..., 1, 0] = w[..., 2]

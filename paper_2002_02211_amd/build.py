@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["push.hip", "field.hip", "api.hip"]
+SOURCES = ["push.hip", "field.hip", "api.hip", "track.hip", "track_api.hip"]
 LIB = os.path.join(HERE, "libspinpic.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 

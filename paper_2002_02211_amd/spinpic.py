@@ -27,7 +27,9 @@ MAX_SPECIES = 4
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
             "pic_spectrum", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
-            "pic_timing", "pic_timing_read", "pic_last_error", "pic_free")
+            "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
+            "pic_track_create", "pic_track_forward", "pic_track_backward", "pic_track_timing",
+            "pic_track_last_error", "pic_track_free")
 
 _ERR_NAMES = {PIC_EINVAL: "PIC_EINVAL", PIC_ECFL: "PIC_ECFL", PIC_EHIP: "PIC_EHIP",
               PIC_ECAPACITY: "PIC_ECAPACITY", PIC_ENONFINITE: "PIC_ENONFINITE",
@@ -62,6 +64,12 @@ class State(ctypes.Structure):
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TrackConfig(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_double), ("mu", ctypes.c_double), ("a", ctypes.c_double),
+                ("dt", ctypes.c_double), ("nsteps", ctypes.c_int32), ("checkpoint", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class Allocator(ctypes.Structure):
@@ -105,12 +113,21 @@ def load_library(path=LIB_PATH):
     lib.pic_timing.argtypes = [P, ctypes.c_int32]
     lib.pic_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.pic_track_create.argtypes = [ctypes.POINTER(TrackConfig), ctypes.c_int64,
+                                     ctypes.POINTER(Allocator), P, ctypes.POINTER(P)]
+    lib.pic_track_forward.argtypes = [P, ctypes.c_double, ctypes.c_double, D, D, D, D, D, D, D]
+    lib.pic_track_backward.argtypes = [P, D, D, D, D, D, D]
+    lib.pic_track_timing.argtypes = [P, D]
+    lib.pic_track_last_error.argtypes = [P]
+    lib.pic_track_last_error.restype = ctypes.c_char_p
+    lib.pic_track_free.argtypes = [P]
+    lib.pic_track_free.restype = None
     lib.pic_last_error.argtypes = [P]
     lib.pic_last_error.restype = ctypes.c_char_p
     lib.pic_free.argtypes = [P]
     lib.pic_free.restype = None
     for name in EXPORTED:
-        if name not in ("pic_last_error", "pic_free"):
+        if name not in ("pic_last_error", "pic_free", "pic_track_last_error", "pic_track_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -372,3 +389,110 @@ class Simulation:
             self.close()
         except Exception:   # noqa: BLE001
             pass
+
+
+# ---------------------------------------------------------------- tracking
+
+def _track_check(code, tr):
+    if code != PIC_OK:
+        msg = load_library().pic_track_last_error(tr)
+        raise PicError(code, msg.decode() if msg else "")
+
+
+def _rows3(a, n, name):
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.shape != (n, 3):
+        raise ValueError("%s must have shape (%d, 3)" % (name, n))
+    return arr
+
+
+class Tracker:
+    """Spin tracking of n test particles through the analytic wakefield, and
+    the gradient of the final polarization (pic_track_*)."""
+
+    def __init__(self, n, Z=1.0, mu=1836.15267343, a=1.793, dt=0.5, nsteps=4000, checkpoint=100,
+                 precision="fp32", device=0):
+        lib = load_library()
+        self.n = int(n)
+        cfg = TrackConfig(float(Z), float(mu), float(a), float(dt), int(nsteps), int(checkpoint),
+                          {"fp64": PIC_FP64, "fp32": PIC_FP32_MIXED}[precision])
+        self._mem = _TorchMemory(device)
+        h = ctypes.c_void_p()
+        _track_check(lib.pic_track_create(ctypes.byref(cfg), self.n, ctypes.byref(self._mem.allocator),
+                                          self._mem.stream_handle, ctypes.byref(h)), None)
+        self.h = h
+        self.generation = 0
+
+    def forward(self, E0, kp, x0, u0, s0, want_state=False):
+        """Final polarization P (3,), and the final x, u, s if asked."""
+        n = self.n
+        x0, u0, s0 = _rows3(x0, n, "x0"), _rows3(u0, n, "u0"), _rows3(s0, n, "s0")
+        P = np.zeros(3)
+        outs = [np.empty((n, 3)) for _ in range(3)] if want_state else [None, None, None]
+        ptr = [_dptr(o) if o is not None else None for o in outs]
+        _track_check(load_library().pic_track_forward(self.h, float(E0), float(kp), _dptr(x0), _dptr(u0),
+                                                      _dptr(s0), _dptr(P), *ptr), self.h)
+        self.generation += 1
+        return (P, *outs) if want_state else P
+
+    def backward(self, c, per_particle_theta=False):
+        """(dJ/dE0, dJ/dkp), dJ/dx0, dJ/du0, dJ/ds0 for J = c . P of the last forward
+        run; with per_particle_theta also each particle's (dJ/dE0, dJ/dkp) share."""
+        n = self.n
+        c = np.ascontiguousarray(c, dtype=np.float64).reshape(3)
+        gth = np.zeros(2)
+        gx, gu, gs = np.empty((n, 3)), np.empty((n, 3)), np.empty((n, 3))
+        each = np.empty((n, 2)) if per_particle_theta else None
+        _track_check(load_library().pic_track_backward(self.h, _dptr(c), _dptr(gth), _dptr(gx), _dptr(gu),
+                                                       _dptr(gs), _dptr(each) if each is not None else None),
+                     self.h)
+        out = (gth, gx, gu, gs)
+        return out + (each,) if per_particle_theta else out
+
+    def timing(self):
+        ms = np.zeros(2)
+        _track_check(load_library().pic_track_timing(self.h, _dptr(ms)), self.h)
+        return {"forward_ms": ms[0], "backward_ms": ms[1]}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load_library().pic_track_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass
+
+
+def wake_polarization(tracker, E0, kp, x0, u0, s0):
+    """Final polarization P (float64 tensor of 3) as a differentiable function
+    of the torch scalars E0, kp and the (n, 3) tensors x0, u0, s0; the
+    backward pass is the library's adjoint (pic_track_backward)."""
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, e0, k, x, u, s):
+            arrs = [t.detach().cpu().double().numpy() for t in (x, u, s)]
+            P = tracker.forward(float(e0), float(k), *arrs)
+            ctx.args = (float(e0), float(k), arrs)
+            ctx.generation = tracker.generation
+            ctx.devices = [t.device for t in (e0, k, x, u, s)]
+            return torch.tensor(P, dtype=torch.float64, device=x.device)
+
+        @staticmethod
+        def backward(ctx, gP):
+            if tracker.generation != ctx.generation:
+                # another forward ran on this tracker since: recompute this one
+                e0, k, arrs = ctx.args
+                tracker.forward(e0, k, *arrs)
+            gth, gx, gu, gs = tracker.backward(gP.detach().cpu().double().numpy())
+            dv = ctx.devices
+            return (torch.tensor(gth[0], dtype=torch.float64, device=dv[0]),
+                    torch.tensor(gth[1], dtype=torch.float64, device=dv[1]),
+                    torch.from_numpy(gx).to(dv[2]), torch.from_numpy(gu).to(dv[3]),
+                    torch.from_numpy(gs).to(dv[4]))
+
+    return _Fn.apply(E0, kp, x0, u0, s0)

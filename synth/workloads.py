@@ -239,3 +239,43 @@ def make_state(spec, with_particles=True):
             np.zeros((0, 10)) for _ in spec["species"]],
         "fields": make_laser_fields(spec),
     }
+
+
+# ---------------------------------------------------------------- test-particle beams
+
+MICRON = LAMBDA / 0.8   # one micrometre in c/omega0 for a 0.8 um laser wavelength
+
+
+def tracking_preset(name="c4", **overrides):
+    """Beam and wake of the differentiable tracking workloads.
+
+    ``c4``: 2^20 protons through a linear wake with E0 = 0.1 m_e c omega0 / e and
+    kp = 0.1 omega0 / c (n = 0.01 n_c), dt = 0.5 / omega0, 4000 steps, states kept
+    every 100 steps.  gamma ~ N(20, 2) along z, x and y ~ N(0, 1 um), z uniform
+    over one plasma wavelength, spins +z.  ``track_small``: 64 of them for 300
+    steps, kept every 40 (so the last segment is short)."""
+    s = {"name": "c4", "n": 1 << 20, "seed": 4, "E0": 0.1, "kp": 0.1, "dt": 0.5, "nsteps": 4000,
+         "checkpoint": 100, "gamma_mean": 20.0, "gamma_std": 2.0, "sigma_r": MICRON,
+         "species": proton(), "s0": (0.0, 0.0, 1.0), "precision": "fp32"}
+    if name == "track_small":
+        s.update({"name": "track_small", "n": 64, "seed": 44, "nsteps": 300, "checkpoint": 40,
+                  "precision": "fp64"})
+    elif name != "c4":
+        raise KeyError(name)
+    s.update(overrides)
+    return s
+
+
+def make_beam(spec):
+    """x0, u0, s0, each (n, 3), of a tracking workload."""
+    rng = np.random.default_rng(spec["seed"])
+    n = int(spec["n"])
+    x = np.empty((n, 3))
+    x[:, 0] = rng.normal(0.0, spec["sigma_r"], n)
+    x[:, 1] = rng.normal(0.0, spec["sigma_r"], n)
+    x[:, 2] = rng.uniform(0.0, 2.0 * math.pi / spec["kp"], n)
+    gamma = np.maximum(rng.normal(spec["gamma_mean"], spec["gamma_std"], n), 1.01)
+    u = np.zeros((n, 3))
+    u[:, 2] = np.sqrt(gamma * gamma - 1.0)
+    s = np.tile(np.asarray(spec["s0"], dtype=np.float64), (n, 1))
+    return x, u, s

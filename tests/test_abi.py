@@ -168,3 +168,25 @@ def test_binding_raises_when_library_missing(tmp_path):
             S.load_library(str(tmp_path / "nope.so"))
     finally:
         S._lib = saved
+
+
+def test_track_calls_validate_without_a_gpu(lib):
+    P = ctypes.c_void_p()
+    good = S.TrackConfig(1.0, 1836.15267343, 1.793, 0.5, 100, 10, S.PIC_FP32_MIXED)
+    assert lib.pic_track_create(ctypes.byref(good), 10, None, None, None) == S.PIC_EINVAL
+    assert lib.pic_track_create(None, 10, None, None, ctypes.byref(P)) == S.PIC_EINVAL
+    bad = [
+        (S.TrackConfig(1.0, 1836.15, 1.793, 0.5, 100, 10, S.PIC_FP32_MIXED), 0, "outside 1.."),
+        (S.TrackConfig(1.0, 0.0, 1.793, 0.5, 100, 10, S.PIC_FP32_MIXED), 10, "mass"),
+        (S.TrackConfig(1.0, 1836.15, 1.793, -0.5, 100, 10, S.PIC_FP32_MIXED), 10, "dt"),
+        (S.TrackConfig(1.0, 1836.15, 1.793, 0.5, -1, 10, S.PIC_FP32_MIXED), 10, "nsteps"),
+        (S.TrackConfig(1.0, 1836.15, 1.793, 0.5, 100, 0, S.PIC_FP32_MIXED), 10, "checkpoint"),
+        (S.TrackConfig(1.0, 1836.15, 1.793, 0.5, 100, 10, 7), 10, "precision"),
+    ]
+    for cfg, n, needle in bad:
+        assert lib.pic_track_create(ctypes.byref(cfg), n, None, None, ctypes.byref(P)) == S.PIC_EINVAL
+        assert needle in lib.pic_track_last_error(None).decode()
+    assert lib.pic_track_forward(None, 0.1, 0.1, None, None, None, None, None, None, None) == S.PIC_ESTATE
+    assert lib.pic_track_backward(None, None, None, None, None, None, None) == S.PIC_ESTATE
+    assert lib.pic_track_timing(None, None) == S.PIC_ESTATE
+    lib.pic_track_free(None)
