@@ -208,6 +208,57 @@ const char* pic_last_error(const pic_ctx* ctx);
 void pic_free(pic_ctx* ctx);
 
 /* ---------------------------------------------------------------------------
+ * Batches: many independent 2D runs of uneven size stepped together.
+ *
+ * The runs share one particle store and concatenated field arrays; a step is
+ * one persistent push over the tiles of every run (largest tiles first, the
+ * workgroups taking tiles from a queue until none is left), one overflow
+ * push, one leaver insertion and three field-update launches, whatever the
+ * number of runs.  Each run is the step of pic_step on its own grid.
+ * ------------------------------------------------------------------------- */
+typedef struct pic_batch pic_batch;
+
+/* nrun runs (1..65535) from cfgs[r], inits[r] (as for pic_init; host memory,
+ * copied).  All runs must be 2D with the same precision, species, flags, deposit_acc
+ * and slack; grids, cell sizes, time steps, tiles and particles may differ.
+ * With autotune != 0 every run whose cfg tile is 0 x 0 gets the square tile
+ * (8, 12, 16, 24 or 32 cells, clipped to the grid, among those whose shared
+ * memory fits) under which its particles were pushed fastest in two timed
+ * steps of the batch built with each candidate; otherwise 16 x 16.  Errors as pic_init, with the run named in pic_batch_last_error. */
+int pic_batch_init(int32_t nrun, const pic_config* cfgs, const pic_state* inits, int32_t autotune,
+                   const pic_allocator* alloc, void* hip_stream, pic_batch** out);
+
+/* Enqueue nsteps >= 0 steps of every run. */
+int pic_batch_step(pic_batch* b, int32_t nsteps);
+
+/* As pic_polarization, pic_fields (E, B, J only) and pic_particles, for run
+ * `run`.  Wait. */
+int pic_batch_polarization(pic_batch* b, int32_t run, int32_t species, double ekin_min_mev,
+                           double ekin_max_mev, double P_out[3], int64_t* N_out);
+int pic_batch_fields(pic_batch* b, int32_t run, uint32_t mask, double* host_out, size_t cap_doubles);
+int pic_batch_particles(pic_batch* b, int32_t run, int32_t species, double* host_out,
+                        size_t cap_doubles, int64_t* n_out);
+
+/* Run `run`: out[0], out[1] its tile, out[2] its particles, out[3] its cells. */
+int pic_batch_info(pic_batch* b, int32_t run, int64_t out[4]);
+
+/* The autotuner's measurements: *ncand_out candidate tile edges into
+ * cand_out (cap_cand >= *ncand_out), and ns_out[r * ncand + c] the push time
+ * per particle-step of run r under candidate c (0 where not tried).
+ * *ncand_out is 0 when nothing was tuned. */
+int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, int32_t cap_cand,
+                     int32_t* ncand_out);
+
+/* As pic_stats (out[5] workgroups of the persistent push, out[6] tiles of
+ * all runs when cap >= 7), pic_timing and pic_timing_read. */
+int pic_batch_stats(pic_batch* b, int64_t* out, int32_t cap);
+int pic_batch_timing(pic_batch* b, int32_t enable);
+int pic_batch_timing_read(pic_batch* b, double* ms_out, int64_t* launches_out, int32_t cap);
+
+const char* pic_batch_last_error(const pic_batch* b);
+void pic_batch_free(pic_batch* b);
+
+/* ---------------------------------------------------------------------------
  * Differentiable test-particle spin tracking.
  *
  * n independent particles of one species cross an analytic linear wake moving

@@ -155,6 +155,61 @@ struct Timer {
     size_t used = 0;
 };
 
+// HIP events around each kernel class on a stream: start/stop pairs recorded
+// while on, summed per class by timer_read.
+void timer_start(Timer& tm, hipStream_t stream, int k) {
+    if (!tm.on) return;
+    if (tm.used + 2 > tm.pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) == hipSuccess) tm.pool.push_back(e);
+        }
+    }
+    if (tm.used + 2 > tm.pool.size()) return;
+    hipEvent_t a = tm.pool[tm.used++];
+    hipEvent_t b = tm.pool[tm.used++];
+    (void)hipEventRecord(a, stream);
+    tm.rec.push_back({k, {a, b}});
+}
+
+void timer_stop(Timer& tm, hipStream_t stream, int k) {
+    if (!tm.on || tm.rec.empty() || tm.rec.back().first != k) return;
+    (void)hipEventRecord(tm.rec.back().second.second, stream);
+}
+
+Status timer_enable(Timer& tm, hipStream_t stream, int enable) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream));
+    tm.on = enable != 0;
+    tm.rec.clear();
+    tm.used = 0;
+    return Status{};
+}
+
+Status timer_read(Timer& tm, hipStream_t stream, double* ms, int64_t* launches, int cap) {
+    if (cap < kTimers) return fail(PIC_EINVAL, "timing_read needs cap >= %d", kTimers);
+    HIP_OR_FAIL(hipStreamSynchronize(stream));
+    double t[kTimers] = {0, 0, 0, 0};
+    int64_t c[kTimers] = {0, 0, 0, 0};
+    for (auto& r : tm.rec) {
+        float e = 0.f;
+        HIP_OR_FAIL(hipEventElapsedTime(&e, r.second.first, r.second.second));
+        t[r.first] += e;
+        c[r.first]++;
+    }
+    for (int i = 0; i < kTimers; ++i) {
+        if (ms) ms[i] = t[i];
+        if (launches) launches[i] = c[i];
+    }
+    return Status{};
+}
+
+void timer_free(Timer& tm) {
+    for (auto& e : tm.pool) (void)hipEventDestroy(e);
+    tm.pool.clear();
+    tm.rec.clear();
+    tm.used = 0;
+}
+
 class EngineBase {
 public:
     virtual ~EngineBase() {}
@@ -313,9 +368,7 @@ void Engine<real, DIM>::free_store(PArrays<real>& a) {
 template <typename real, int DIM>
 void Engine<real, DIM>::release() {
     if (stream_ != nullptr || !live_.empty()) (void)hipStreamSynchronize(stream_);
-    for (auto& e : timer_.pool) (void)hipEventDestroy(e);
-    timer_.pool.clear();
-    timer_.rec.clear();
+    timer_free(timer_);
     std::vector<void*> all = live_;
     for (void* p : all) dfree(p);
     live_.clear();
@@ -584,24 +637,12 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
 
 template <typename real, int DIM>
 void Engine<real, DIM>::tstart(int k) {
-    if (!timer_.on) return;
-    if (timer_.used + 2 > timer_.pool.size()) {
-        for (int i = 0; i < 64; ++i) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) == hipSuccess) timer_.pool.push_back(e);
-        }
-    }
-    if (timer_.used + 2 > timer_.pool.size()) return;
-    hipEvent_t a = timer_.pool[timer_.used++];
-    hipEvent_t b = timer_.pool[timer_.used++];
-    (void)hipEventRecord(a, stream_);
-    timer_.rec.push_back({k, {a, b}});
+    timer_start(timer_, stream_, k);
 }
 
 template <typename real, int DIM>
 void Engine<real, DIM>::tstop(int k) {
-    if (!timer_.on || timer_.rec.empty() || timer_.rec.back().first != k) return;
-    (void)hipEventRecord(timer_.rec.back().second.second, stream_);
+    timer_stop(timer_, stream_, k);
 }
 
 template <typename real, int DIM>
@@ -1007,29 +1048,715 @@ Status Engine<real, DIM>::stats(int64_t* out, int cap) {
 
 template <typename real, int DIM>
 Status Engine<real, DIM>::timing(int enable) {
-    HIP_OR_FAIL(hipStreamSynchronize(stream_));
-    timer_.on = enable != 0;
-    timer_.rec.clear();
-    timer_.used = 0;
-    return Status{};
+    return timer_enable(timer_, stream_, enable);
 }
 
 template <typename real, int DIM>
 Status Engine<real, DIM>::timing_read(double* ms, int64_t* launches, int cap) {
-    if (cap < kTimers) return fail(PIC_EINVAL, "timing_read needs cap >= %d", kTimers);
+    return timer_read(timer_, stream_, ms, launches, cap);
+}
+
+// ---------------------------------------------------------------- batches
+
+// Independent 2D runs of uneven size in shared stores: one segment list, one
+// particle store and concatenated field arrays, each run at its own offsets.
+// A step is one persistent push over all runs' tiles (largest first), one
+// overflow push, one leaver insertion and the three field-update launches
+// over all runs at once.
+class BatchBase {
+public:
+    virtual ~BatchBase() {}
+    virtual Status step(int n) = 0;
+    virtual Status polarization(int run, int species, double emin, double emax, double P[3], int64_t* N) = 0;
+    virtual Status fields(int run, uint32_t mask, double* out, size_t cap) = 0;
+    virtual Status particles(int run, int species, double* out, size_t cap, int64_t* n) = 0;
+    virtual Status stats(int64_t* out, int cap) = 0;
+    virtual Status run_time(bool enable, double* ns_out) = 0;
+    virtual Status timing(int enable) = 0;
+    virtual Status timing_read(double* ms, int64_t* launches, int cap) = 0;
+    virtual void run_info(int r, int64_t* out) const = 0;   // tile x, tile y, particles, cells
+    virtual int nruns() const = 0;
+};
+
+template <typename real>
+class BatchEngine : public BatchBase {
+public:
+    BatchEngine(const pic_allocator* alloc, hipStream_t stream) : stream_(stream) {
+        if (alloc && alloc->alloc && alloc->free) {
+            alloc_ = *alloc;
+            has_alloc_ = true;
+        }
+    }
+    ~BatchEngine() { release(); }
+
+    struct Run {
+        Resolved R;
+        Geom g;
+        double d[3];
+        long long cell_off = 0;
+        int sid_base = 0, tile_base = 0;
+        long long count_sp[kMaxSpecies] = {0, 0, 0, 0};
+        long long npart = 0;
+    };
+
+    Status init(const std::vector<Resolved>& Rs, const pic_state* st);
+    Status step(int nsteps) override;
+    Status polarization(int run, int species, double emin, double emax, double P[3], int64_t* N) override;
+    Status fields(int run, uint32_t mask, double* out, size_t cap) override;
+    Status particles(int run, int species, double* out, size_t cap, int64_t* n) override;
+    Status stats(int64_t* out, int cap) override;
+    Status run_time(bool enable, double* ns_out) override;   // per-run push time while enabled
+    Status timing(int enable) override { return timer_enable(timer_, stream_, enable); }
+    Status timing_read(double* ms, int64_t* launches, int cap) override {
+        return timer_read(timer_, stream_, ms, launches, cap);
+    }
+    void run_info(int r, int64_t* out) const override {
+        out[0] = runs_[r].g.T[0];
+        out[1] = runs_[r].g.T[1];
+        out[2] = runs_[r].npart;
+        out[3] = runs_[r].g.ncells;
+    }
+    int nruns() const override { return (int)runs_.size(); }
+    void release();
+
+private:
+    void* dalloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void* p = nullptr;
+        if (has_alloc_) p = alloc_.alloc(alloc_.user, bytes);
+        else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+        if (p) live_.push_back(p);
+        return p;
+    }
+    void dfree(void* p) {
+        if (!p) return;
+        auto it = std::find(live_.begin(), live_.end(), p);
+        if (it != live_.end()) live_.erase(it);
+        if (has_alloc_) alloc_.free(alloc_.user, p);
+        else (void)hipFree(p);
+    }
+    Status alloc_store(PArrays<real>& a, long long cap, bool with_species);
+    void free_store(PArrays<real>& a);
+    Status repack();
+    Status upload_descs();
+    size_t push_lds() const {
+        size_t lds = 0;
+        for (const Run& r : runs_) {
+            const size_t l = use_acc64_ ? tile_lds_bytes<real, double>(r.g, seg_.max_chunks)
+                                        : tile_lds_bytes<real, real>(r.g, seg_.max_chunks);
+            lds = std::max(lds, l);
+        }
+        return lds;
+    }
+
+    pic_allocator alloc_{};
+    bool has_alloc_ = false;
+    hipStream_t stream_;
+    std::vector<void*> live_;
+    std::vector<Run> runs_;
+    int nsp_ = 0, nseg_ = 0, ntiles_ = 0, nx_max_ = 1, ny_max_ = 1;
+    int use_acc64_ = 1, deposit_ = 1;
+    long long cap_total_ = 0, npart_ = 0, ncells_ = 0;
+    int64_t nstep_ = 0, repacks_ = 0;
+    int push_blocks_ = 1;
+    PArrays<real> p_{}, lv_{}, st_{};
+    Segs seg_{};
+    Fields<freal> f_{};
+    freal* jbuf_[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int jcur_ = 0;
+    int32_t* ctr_ = nullptr;
+    int32_t* h_ctr_ = nullptr;
+    unsigned long long* moved_ = nullptr;
+    unsigned long long* run_ns_ = nullptr;
+    bool time_runs_ = false;
+    double* acc_ = nullptr;
+    RunDesc<real>* d_runs_ = nullptr;
+    TileRef* d_order_ = nullptr;
+    std::vector<TileRef> order_;
+    Timer timer_;
+};
+
+template <typename real>
+Status BatchEngine<real>::alloc_store(PArrays<real>& a, long long cap, bool with_species) {
+    a = PArrays<real>{};
+    const size_t n = (size_t)std::max(cap, 1LL);
+    a.cell = (int32_t*)dalloc(n * sizeof(int32_t));
+    for (int d = 0; d < 2; ++d) a.off[d] = (real*)dalloc(n * sizeof(real));
+    for (int d = 0; d < 3; ++d) {
+        a.u[d] = (real*)dalloc(n * sizeof(real));
+        a.s[d] = (real*)dalloc(n * sizeof(real));
+    }
+    a.w = (real*)dalloc(n * sizeof(real));
+    a.id = (int32_t*)dalloc(n * sizeof(int32_t));
+    if (with_species) a.sp = (int32_t*)dalloc(n * sizeof(int32_t));
+    bool ok = a.cell && a.w && a.id && a.off[0] && a.off[1] && (!with_species || a.sp);
+    for (int d = 0; d < 3; ++d) ok = ok && a.u[d] && a.s[d];
+    if (!ok) return fail(PIC_ENOMEM, "device allocation of a particle store (%lld slots) failed", cap);
+    return Status{};
+}
+
+template <typename real>
+void BatchEngine<real>::free_store(PArrays<real>& a) {
+    dfree(a.cell);
+    for (int d = 0; d < 3; ++d) {
+        dfree(a.off[d]);
+        dfree(a.u[d]);
+        dfree(a.s[d]);
+    }
+    dfree(a.w);
+    dfree(a.id);
+    dfree(a.sp);
+    a = PArrays<real>{};
+}
+
+template <typename real>
+void BatchEngine<real>::release() {
+    if (stream_ != nullptr || !live_.empty()) (void)hipStreamSynchronize(stream_);
+    timer_free(timer_);
+    std::vector<void*> all = live_;
+    for (void* p : all) dfree(p);
+    live_.clear();
+    if (h_ctr_) (void)hipHostFree(h_ctr_);
+    h_ctr_ = nullptr;
+}
+
+template <typename real>
+Status BatchEngine<real>::upload_descs() {
+    std::vector<RunDesc<real>> d(runs_.size());
+    for (size_t r = 0; r < runs_.size(); ++r) {
+        const Run& R = runs_[r];
+        const pic_config& c = R.R.cfg;
+        RunDesc<real>& D = d[r];
+        D = RunDesc<real>{};
+        D.g = R.g;
+        D.k.dt = (real)c.dt;
+        D.kf.dt = c.dt;
+        for (int a = 0; a < 3; ++a) {
+            D.k.dt_d[a] = (real)(c.dt / R.d[a]);
+            D.k.d_dt[a] = (real)(R.d[a] / c.dt);
+            D.kf.cb[a] = 0.5 * c.dt / R.d[a];
+            D.kf.ce[a] = c.dt / R.d[a];
+        }
+        for (int s = 0; s < kMaxSpecies; ++s) {
+            const bool on = s < c.nspecies;
+            const double rr = on ? c.sp[s].Z / c.sp[s].mu : 0.0;
+            D.k.r[s] = (real)rr;
+            D.k.eps[s] = (real)(0.5 * rr * c.dt);
+            D.k.a[s] = on ? (real)c.sp[s].a : real(0);
+            D.k.Z[s] = on ? (real)c.sp[s].Z : real(0);
+        }
+        D.cell_off = R.cell_off;
+        D.sid_base = R.sid_base;
+        D.tile_base = R.tile_base;
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(d_runs_, d.data(), d.size() * sizeof(RunDesc<real>), hipMemcpyHostToDevice, stream_));
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state* st) {
+    const int nrun = (int)Rs.size();
+    runs_.resize(nrun);
+    nsp_ = Rs[0].cfg.nspecies;
+    use_acc64_ = Rs[0].use_acc64;
+    deposit_ = (Rs[0].cfg.flags & PIC_FLAG_TEST_PARTICLE) ? 0 : 1;
+    // ---- layout: tiles, segments and cells of every run, one after another
+    long long cells = 0;
+    int sids = 0, tiles = 0;
+    npart_ = 0;
+    for (int r = 0; r < nrun; ++r) {
+        Run& R = runs_[r];
+        R.R = Rs[r];
+        const pic_config& c = R.R.cfg;
+        R.g = Geom{};
+        R.g.ndim = 2;
+        R.g.nsp = nsp_;
+        for (int a = 0; a < 3; ++a) {
+            R.g.n[a] = R.R.n[a];
+            R.g.T[a] = R.R.T[a];
+            R.g.nt[a] = R.R.nt[a];
+            R.d[a] = a < 2 ? c.d[a] : 1.0;
+        }
+        R.g.ntiles = R.g.nt[0] * R.g.nt[1];
+        R.g.ncells = (long long)R.g.n[0] * R.g.n[1];
+        R.cell_off = cells;
+        R.sid_base = sids;
+        R.tile_base = tiles;
+        cells += R.g.ncells;
+        sids += R.g.ntiles * nsp_;
+        tiles += R.g.ntiles;
+        nx_max_ = std::max(nx_max_, R.g.n[0]);
+        ny_max_ = std::max(ny_max_, R.g.n[1]);
+        R.npart = 0;
+        for (int s = 0; s < nsp_; ++s) {
+            R.count_sp[s] = st[r].count[s];
+            R.npart += R.count_sp[s];
+        }
+        npart_ += R.npart;
+    }
+    ncells_ = cells;
+    nseg_ = sids;
+    ntiles_ = tiles;
+    if (npart_ > (1LL << 31) - 1) return fail(PIC_EINVAL, "more than 2^31 particles in the batch");
+
+    // ---- bin every particle: global segment and an in-segment order key
+    std::vector<long long> count(nseg_, 0);
+    std::vector<int32_t> segof((size_t)npart_);
+    std::vector<uint32_t> key((size_t)npart_);
+    std::vector<long long> run_first(nrun + 1, 0);
+    auto place = [](const double* row, const Run& R, int cell[2], double off[2]) {
+        for (int a = 0; a < 2; ++a) {
+            const double xi = row[a] / R.d[a];
+            const double fl = std::floor(xi);
+            double o = xi - fl;
+            long long ci = (long long)fl % R.g.n[a];
+            if (ci < 0) ci += R.g.n[a];
+            if ((real)o >= real(1)) {
+                o = 0.0;
+                ci = (ci + 1) % R.g.n[a];
+            }
+            cell[a] = (int)ci;
+            off[a] = o;
+        }
+    };
+    {
+        long long q = 0;
+        for (int r = 0; r < nrun; ++r) {
+            Run& R = runs_[r];
+            run_first[r] = q;
+            const int tile_cells = R.g.T[0] * R.g.T[1];
+            std::vector<int32_t> cellrank((size_t)nsp_ * R.g.ncells, 0);
+            for (int s = 0; s < nsp_; ++s) {
+                const double* P = st[r].particles[s];
+                for (long long i = 0; i < R.count_sp[s]; ++i, ++q) {
+                    const double* row = P + i * PIC_PARTICLE_IN_COLS;
+                    for (int col = 0; col < PIC_PARTICLE_IN_COLS; ++col)
+                        if (!std::isfinite(row[col]))
+                            return fail(PIC_EINVAL, "run %d species %d particle %lld: non-finite input", r, s, i);
+                    const double s2 = row[6] * row[6] + row[7] * row[7] + row[8] * row[8];
+                    if (std::fabs(s2 - 1.0) > 1e-6)
+                        return fail(PIC_EINVAL, "run %d species %d particle %lld: |s| must be 1", r, s, i);
+                    int cell[2];
+                    double off[2];
+                    place(row, R, cell, off);
+                    const int tile = cell[0] / R.g.T[0] + R.g.nt[0] * (cell[1] / R.g.T[1]);
+                    const int sid = R.sid_base + tile * nsp_ + s;
+                    segof[q] = sid;
+                    count[sid]++;
+                    const long long gcell = (long long)cell[1] * R.g.n[0] + cell[0];
+                    const long long rank = cellrank[(size_t)s * R.g.ncells + gcell]++;
+                    const int lc = (cell[0] % R.g.T[0]) + R.g.T[0] * (cell[1] % R.g.T[1]);
+                    const unsigned long long k64 = (unsigned long long)rank * tile_cells + lc;
+                    if (k64 > 0xFFFFFFFFull) return fail(PIC_EINVAL, "more than 2^32 particle ranks in a tile");
+                    key[q] = (uint32_t)k64;
+                }
+            }
+        }
+        run_first[nrun] = q;
+    }
+    std::vector<int32_t> h_start(nseg_), h_cap(nseg_), h_count(nseg_);
+    cap_total_ = 0;
+    long long maxcap = 0;
+    for (int s = 0; s < nseg_; ++s) {
+        const double slack = runs_[0].R.slack;
+        const long long cp = seg_capacity(count[s], slack);
+        h_start[s] = (int32_t)cap_total_;
+        h_cap[s] = (int32_t)cp;
+        h_count[s] = (int32_t)count[s];
+        cap_total_ += cp;
+        maxcap = std::max(maxcap, cp);
+        if (cap_total_ > kMaxSlots) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^29 slots");
+    }
+    seg_.dummy = (int)cap_total_;
+    seg_.max_chunks = (int)((maxcap + 63) / 64);
+    if (push_lds() > 64 * 1024) return fail(PIC_ECAPACITY, "a tile needs more than 64 KiB of shared memory");
+
+    // ---- device memory
+    Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
+    if (S.code) return S;
+    S = alloc_store(lv_, std::max(npart_, 1LL), true);
+    if (S.code) return S;
+    S = alloc_store(st_, std::max(npart_, 1LL), true);
+    if (S.code) return S;
+    seg_.start = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    seg_.cap = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    seg_.count = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    for (int a = 0; a < 3; ++a) {
+        f_.E[a] = (freal*)dalloc(ncells_ * sizeof(freal));
+        f_.B[a] = (freal*)dalloc(ncells_ * sizeof(freal));
+        for (int b = 0; b < 2; ++b) jbuf_[b][a] = (freal*)dalloc(ncells_ * sizeof(freal));
+        f_.J[a] = jbuf_[0][a];
+    }
+    ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
+    moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
+    run_ns_ = (unsigned long long*)dalloc(nrun * sizeof(unsigned long long));
+    acc_ = (double*)dalloc(8 * sizeof(double));
+    d_runs_ = (RunDesc<real>*)dalloc(nrun * sizeof(RunDesc<real>));
+    d_order_ = (TileRef*)dalloc(ntiles_ * sizeof(TileRef));
+    bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && run_ns_ && acc_ && d_runs_ && d_order_;
+    for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
+    if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
+    HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
+    std::memset(h_ctr_, 0, CTR_NCTR * sizeof(int32_t));
+
+    // ---- particles in segment order
+    {
+        const size_t C = (size_t)cap_total_;
+        std::vector<int32_t> hcell(C, 0), hid(C, 0);
+        std::vector<real> hoff[2], hu[3], hs[3], hw(C, real(0));
+        for (int a = 0; a < 2; ++a) hoff[a].assign(C, real(0));
+        for (int a = 0; a < 3; ++a) {
+            hu[a].assign(C, real(0));
+            hs[a].assign(C, real(0));
+        }
+        std::vector<uint32_t> perm((size_t)npart_);
+        std::vector<long long> first(nseg_ + 1, 0), fill(nseg_, 0);
+        for (int sg = 0; sg < nseg_; ++sg) first[sg + 1] = first[sg] + count[sg];
+        for (long long q = 0; q < npart_; ++q) perm[first[segof[q]] + fill[segof[q]]++] = (uint32_t)q;
+        for (int sg = 0; sg < nseg_; ++sg)
+            std::sort(perm.begin() + first[sg], perm.begin() + first[sg + 1],
+                      [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+        for (int r = 0; r < nrun; ++r) {
+            const Run& R = runs_[r];
+            std::vector<long long> spbase(nsp_ + 1, run_first[r]);
+            for (int s = 0; s < nsp_; ++s) spbase[s + 1] = spbase[s] + R.count_sp[s];
+            for (int sg = R.sid_base; sg < R.sid_base + R.g.ntiles * nsp_; ++sg) {
+                const int s = (sg - R.sid_base) % nsp_;
+                const double* P = st[r].particles[s];
+                long long slot = h_start[sg];
+                for (long long m = first[sg]; m < first[sg + 1]; ++m, ++slot) {
+                    const long long i = (long long)perm[m] - spbase[s];
+                    const double* row = P + i * PIC_PARTICLE_IN_COLS;
+                    int cell[2];
+                    double off[2];
+                    place(row, R, cell, off);
+                    hcell[slot] = pack_cell<2>(cell[0], cell[1], 0);
+                    for (int a = 0; a < 2; ++a) hoff[a][slot] = (real)off[a];
+                    for (int a = 0; a < 3; ++a) {
+                        hu[a][slot] = (real)row[3 + a];
+                        hs[a][slot] = (real)row[6 + a];
+                    }
+                    hw[slot] = (real)row[9];
+                    hid[slot] = (int32_t)i;
+                }
+            }
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(p_.cell, hcell.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+        HIP_OR_FAIL(hipMemcpyAsync(p_.id, hid.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+        HIP_OR_FAIL(hipMemcpyAsync(p_.w, hw.data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+        for (int a = 0; a < 3; ++a) {
+            if (a < 2)
+                HIP_OR_FAIL(hipMemcpyAsync(p_.off[a], hoff[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+            HIP_OR_FAIL(hipMemcpyAsync(p_.u[a], hu[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+            HIP_OR_FAIL(hipMemcpyAsync(p_.s[a], hs[a].data(), C * sizeof(real), hipMemcpyHostToDevice, stream_));
+        }
+        HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, h_start.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, h_cap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.count, h_count.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemsetAsync(ctr_, 0, CTR_NCTR * sizeof(int32_t), stream_));
+    HIP_OR_FAIL(hipMemsetAsync(moved_, 0, sizeof(unsigned long long), stream_));
+    HIP_OR_FAIL(hipMemsetAsync(run_ns_, 0, nrun * sizeof(unsigned long long), stream_));
+
+    // ---- fields, concatenated
+    for (int comp = 0; comp < 6; ++comp) {
+        freal* dst = comp < 3 ? f_.E[comp] : f_.B[comp - 3];
+        for (int r = 0; r < nrun; ++r) {
+            const Run& R = runs_[r];
+            const size_t N = (size_t)R.g.ncells;
+            if (st[r].fields) {
+                const double* src = st[r].fields + comp * N;
+                for (size_t i = 0; i < N; ++i)
+                    if (!std::isfinite(src[i])) return fail(PIC_EINVAL, "run %d field %d: non-finite value", r, comp);
+                HIP_OR_FAIL(hipMemcpyAsync(dst + R.cell_off, src, N * sizeof(freal), hipMemcpyHostToDevice, stream_));
+                HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            } else {
+                HIP_OR_FAIL(hipMemsetAsync(dst + R.cell_off, 0, N * sizeof(freal), stream_));
+            }
+        }
+    }
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 3; ++a) HIP_OR_FAIL(hipMemsetAsync(jbuf_[b][a], 0, ncells_ * sizeof(freal), stream_));
+
+    // ---- tiles largest first, run descriptors, persistent grid size
+    std::vector<std::pair<long long, TileRef>> cost(ntiles_);
+    for (int r = 0; r < nrun; ++r) {
+        const Run& R = runs_[r];
+        for (int t = 0; t < R.g.ntiles; ++t) {
+            long long c = 0;
+            for (int s = 0; s < nsp_; ++s) c += count[R.sid_base + t * nsp_ + s];
+            cost[R.tile_base + t] = {c, TileRef{r, t}};
+        }
+    }
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<long long, TileRef>& a, const std::pair<long long, TileRef>& b) {
+                         return a.first > b.first;
+                     });
+    order_.resize(ntiles_);
+    for (int i = 0; i < ntiles_; ++i) order_[i] = cost[i].second;
+    HIP_OR_FAIL(hipMemcpyAsync(d_order_, order_.data(), ntiles_ * sizeof(TileRef), hipMemcpyHostToDevice, stream_));
+    S = upload_descs();
+    if (S.code) return S;
+    int dev = 0, cus = 256;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = use_acc64_ ? push_batch_blocks_per_cu<real, double>(push_lds())
+                                  : push_batch_blocks_per_cu<real, real>(push_lds());
+    push_blocks_ = std::max(1, std::min(ntiles_, cus * per_cu));
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
-    double t[kTimers] = {0, 0, 0, 0};
-    int64_t c[kTimers] = {0, 0, 0, 0};
-    for (auto& r : timer_.rec) {
-        float e = 0.f;
-        HIP_OR_FAIL(hipEventElapsedTime(&e, r.second.first, r.second.second));
-        t[r.first] += e;
-        c[r.first]++;
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::step(int nsteps) {
+    for (int it = 0; it < nsteps; ++it) {
+        if ((nstep_ & 63) == 0 && h_ctr_[CTR_STASH] > 0) {
+            Status S = repack();
+            if (S.code) return S;
+        }
+        const int slot = (int)(nstep_ & 1);
+        const int jnext = jcur_ ^ 1;
+        for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jnext][a];
+        const size_t lds = push_lds();
+        unsigned long long* rn = time_runs_ ? run_ns_ : nullptr;
+        timer_start(timer_, stream_, 0);
+        if (use_acc64_)
+            HIP_OR_FAIL((launch_push_tiles_batch<real, double>(d_runs_, d_order_, ntiles_, push_blocks_, lds, p_, seg_,
+                                                               lv_, ctr_, slot, f_, deposit_, rn, stream_)));
+        else
+            HIP_OR_FAIL((launch_push_tiles_batch<real, real>(d_runs_, d_order_, ntiles_, push_blocks_, lds, p_, seg_,
+                                                             lv_, ctr_, slot, f_, deposit_, rn, stream_)));
+        timer_stop(timer_, stream_, 0);
+        timer_start(timer_, stream_, 1);
+        HIP_OR_FAIL((launch_push_stash_batch<real>(d_runs_, st_, ctr_, f_, deposit_, 64, stream_)));
+        timer_stop(timer_, stream_, 1);
+        timer_start(timer_, stream_, 2);
+        HIP_OR_FAIL((launch_insert_batch<real>(d_runs_, p_, seg_, lv_, st_, ctr_, slot, moved_, 1024, stream_)));
+        timer_stop(timer_, stream_, 2);
+        if (deposit_) {
+            timer_start(timer_, stream_, 3);
+            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_e_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, jbuf_[jcur_], stream_)));
+            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, stream_)));
+            timer_stop(timer_, stream_, 3);
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost, stream_));
+        if (deposit_) jcur_ = jnext;
+        for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
+        ++nstep_;
     }
-    for (int i = 0; i < kTimers; ++i) {
-        if (ms) ms[i] = t[i];
-        if (launches) launches[i] = c[i];
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::repack() {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
+    h_ctr_[CTR_STASH] = nst;
+    if (nst == 0) return Status{};
+    std::vector<int32_t> cnt(nseg_);
+    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> scell(nst), stag(nst);
+    HIP_OR_FAIL(hipMemcpy(scell.data(), st_.cell, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(stag.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<long long> want(cnt.begin(), cnt.end());
+    for (int i = 0; i < nst; ++i) {
+        const int run = stag[i] / kMaxSpecies, sp = stag[i] % kMaxSpecies;
+        const Run& R = runs_[run];
+        int c[3];
+        unpack_cell<2>(scell[i], c[0], c[1], c[2]);
+        const int tile = c[0] / R.g.T[0] + R.g.nt[0] * (c[1] / R.g.T[1]);
+        want[R.sid_base + tile * nsp_ + sp]++;
     }
+    std::vector<int32_t> nstart(nseg_), ncap(nseg_);
+    long long total = 0, maxcap = 0;
+    for (int s = 0; s < nseg_; ++s) {
+        const long long cp = seg_capacity(want[s], runs_[0].R.slack);
+        nstart[s] = (int32_t)total;
+        ncap[s] = (int32_t)cp;
+        total += cp;
+        maxcap = std::max(maxcap, cp);
+        if (total > kMaxSlots) return fail(PIC_ECAPACITY, "particle capacity exceeds 2^29 slots");
+    }
+    {
+        const int saved = seg_.max_chunks;
+        seg_.max_chunks = (int)((maxcap + 63) / 64);
+        const size_t lds = push_lds();
+        seg_.max_chunks = saved;
+        if (lds > 64 * 1024) return fail(PIC_ECAPACITY, "a tile segment needs more than 64 KiB of shared memory");
+    }
+    PArrays<real> np{};
+    Status S = alloc_store(np, total + kSpareSlots, false);
+    if (S.code) return S;
+    int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
+    if (!d_nstart) return fail(PIC_ENOMEM, "repack allocation failed");
+    HIP_OR_FAIL(hipMemcpyAsync(d_nstart, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL((launch_repack_segments<real>(p_, np, seg_.start, d_nstart, seg_.count, nseg_, 2, stream_)));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, ncap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL((launch_insert_batch<real>(d_runs_, np, seg_, st_, st_, ctr_, CTR_STASH, moved_, 256, stream_)));
+    HIP_OR_FAIL(hipMemsetAsync(ctr_ + CTR_STASH, 0, sizeof(int32_t), stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    free_store(p_);
+    dfree(d_nstart);
+    p_ = np;
+    cap_total_ = total;
+    seg_.dummy = (int)total;
+    seg_.max_chunks = (int)((maxcap + 63) / 64);
+    h_ctr_[CTR_STASH] = 0;
+    repacks_++;
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::polarization(int run, int species, double emin, double emax, double P[3], int64_t* N) {
+    if (run < 0 || run >= nruns()) return fail(PIC_EINVAL, "run %d out of range", run);
+    if (species < -1 || species >= nsp_) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (std::isnan(emin) || std::isnan(emax)) return fail(PIC_EINVAL, "energy window is NaN");
+    const Run& R = runs_[run];
+    ReduceArgs ra{};
+    ra.run = run;
+    ra.species = species;
+    ra.emin = emin;
+    ra.emax = emax;
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        ra.mu[s] = s < nsp_ ? R.R.cfg.sp[s].mu : 1.0;
+        ra.Z[s] = s < nsp_ ? R.R.cfg.sp[s].Z : 0.0;
+    }
+    Segs view = seg_;
+    view.start = seg_.start + R.sid_base;
+    view.cap = seg_.cap + R.sid_base;
+    view.count = seg_.count + R.sid_base;
+    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+    HIP_OR_FAIL((launch_reduce_particles<real, 2>(RED_POLARIZATION, R.g, p_, view, st_, ctr_, ra, acc_, nullptr, stream_)));
+    double acc[8];
+    HIP_OR_FAIL(hipMemcpyAsync(acc, acc_, sizeof acc, hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    *N = (int64_t)std::llround(acc[3]);
+    for (int a = 0; a < 3; ++a) P[a] = acc[3] > 0 ? acc[a] / acc[3] : 0.0;
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::fields(int run, uint32_t mask, double* out, size_t cap) {
+    if (run < 0 || run >= nruns()) return fail(PIC_EINVAL, "run %d out of range", run);
+    if (mask & ~0x1FFu) return fail(PIC_EINVAL, "field mask 0x%x: E, B and J only", mask);
+    const Run& R = runs_[run];
+    const size_t N = (size_t)R.g.ncells;
+    int nc = 0;
+    for (int b = 0; b < 9; ++b) nc += (mask >> b) & 1;
+    if (!out && nc) return fail(PIC_EINVAL, "host_out is NULL");
+    if (cap < (size_t)nc * N) return fail(PIC_EINVAL, "cap %zu < %zu", cap, (size_t)nc * N);
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    size_t o = 0;
+    for (int b = 0; b < 9; ++b) {
+        if (!((mask >> b) & 1)) continue;
+        const freal* src = b < 3 ? f_.E[b] : (b < 6 ? f_.B[b - 3] : f_.J[b - 6]);
+        HIP_OR_FAIL(hipMemcpy(out + o, src + R.cell_off, N * sizeof(freal), hipMemcpyDeviceToHost));
+        o += N;
+    }
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::particles(int run, int species, double* out, size_t cap, int64_t* n_out) {
+    if (run < 0 || run >= nruns()) return fail(PIC_EINVAL, "run %d out of range", run);
+    if (species < 0 || species >= nsp_) return fail(PIC_EINVAL, "species %d out of range", species);
+    const Run& R = runs_[run];
+    const long long n = R.count_sp[species];
+    if (n_out) *n_out = n;
+    if (cap < (size_t)n * PIC_PARTICLE_OUT_COLS) return fail(PIC_EINVAL, "cap too small for %lld particles", n);
+    if (n > 0 && !out) return fail(PIC_EINVAL, "host_out is NULL");
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    const int ns = R.g.ntiles * nsp_;
+    std::vector<int32_t> start(ns), count(ns);
+    HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start + R.sid_base, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(count.data(), seg_.count + R.sid_base, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<char> seen((size_t)n, 0);
+    auto emit_range = [&](const PArrays<real>& A, long long lo, long long hi, bool stash) -> Status {
+        const long long len = hi - lo;
+        if (len <= 0) return Status{};
+        std::vector<int32_t> cell(len), id(len), tag;
+        std::vector<real> off[2], u[3], s[3], w(len);
+        HIP_OR_FAIL(hipMemcpy(cell.data(), A.cell + lo, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(id.data(), A.id + lo, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(w.data(), A.w + lo, len * sizeof(real), hipMemcpyDeviceToHost));
+        if (stash) {
+            tag.resize(len);
+            HIP_OR_FAIL(hipMemcpy(tag.data(), A.sp + lo, len * sizeof(int32_t), hipMemcpyDeviceToHost));
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (a < 2) {
+                off[a].resize(len);
+                HIP_OR_FAIL(hipMemcpy(off[a].data(), A.off[a] + lo, len * sizeof(real), hipMemcpyDeviceToHost));
+            }
+            u[a].resize(len);
+            s[a].resize(len);
+            HIP_OR_FAIL(hipMemcpy(u[a].data(), A.u[a] + lo, len * sizeof(real), hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(hipMemcpy(s[a].data(), A.s[a] + lo, len * sizeof(real), hipMemcpyDeviceToHost));
+        }
+        for (long long q = 0; q < len; ++q) {
+            if (stash && tag[q] != run * kMaxSpecies + species) continue;
+            const long long i = id[q];
+            if (i < 0 || i >= n || seen[i]) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (id %lld)", i);
+            seen[i] = 1;
+            double* row = out + i * PIC_PARTICLE_OUT_COLS;
+            int c[3];
+            unpack_cell<2>(cell[q], c[0], c[1], c[2]);
+            row[0] = (double)i;
+            for (int a = 0; a < 3; ++a) row[1 + a] = a < 2 ? ((double)c[a] + (double)off[a][q]) * R.d[a] : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                row[4 + a] = (double)u[a][q];
+                row[7 + a] = (double)s[a][q];
+            }
+            row[10] = (double)w[q];
+        }
+        return Status{};
+    };
+    for (int t = 0; t < R.g.ntiles; ++t) {
+        const int k = t * nsp_ + species;
+        Status S = emit_range(p_, start[k], (long long)start[k] + count[k], false);
+        if (S.code) return S;
+    }
+    Status S = emit_range(st_, 0, nst, true);
+    if (S.code) return S;
+    for (long long i = 0; i < n; ++i)
+        if (!seen[i]) return fail(PIC_ESTATE, "particle %lld of run %d species %d is missing", i, run, species);
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::stats(int64_t* out, int cap) {
+    if (!out || cap < 5) return fail(PIC_EINVAL, "stats needs cap >= 5");
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    unsigned long long moved = 0;
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&moved, moved_, sizeof moved, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    out[0] = nstep_;
+    out[1] = (int64_t)moved;
+    out[2] = nst;
+    out[3] = repacks_;
+    out[4] = npart_;
+    if (cap > 5) out[5] = push_blocks_;
+    if (cap > 6) out[6] = ntiles_;
+    return Status{};
+}
+
+template <typename real>
+Status BatchEngine<real>::run_time(bool enable, double* ns_out) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    if (ns_out) {
+        std::vector<unsigned long long> h(runs_.size());
+        HIP_OR_FAIL(hipMemcpy(h.data(), run_ns_, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        for (size_t r = 0; r < h.size(); ++r) ns_out[r] = (double)h[r];
+    }
+    HIP_OR_FAIL(hipMemset(run_ns_, 0, runs_.size() * sizeof(unsigned long long)));
+    time_runs_ = enable;
     return Status{};
 }
 
@@ -1176,6 +1903,244 @@ void pic_free(pic_ctx* ctx) {
     if (!ctx) return;
     if (ctx->eng) ctx->eng->release();
     delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches: C ABI
+
+struct pic_batch {
+    std::unique_ptr<BatchBase> eng;
+    std::string err;
+    bool failed = false;
+    std::vector<int32_t> cands;       // tile edges tried by the autotuner
+    std::vector<double> tune;         // nrun x ncand: ns of push per particle-step (0: not tried)
+};
+
+namespace {
+
+constexpr int kTileCandidates[] = {8, 12, 16, 24, 32};
+
+Status batch_resolve(int32_t nrun, const pic_config* cfgs, const pic_state* inits, std::vector<Resolved>& Rs) {
+    Rs.resize(nrun);
+    for (int r = 0; r < nrun; ++r) {
+        Status S = resolve_config(&cfgs[r], &inits[r], Rs[r]);
+        if (S.code) return fail(S.code, "run %d: %s", r, S.msg.c_str());
+        const pic_config& c = cfgs[r];
+        const pic_config& c0 = cfgs[0];
+        if (c.ndim != 2) return fail(PIC_EINVAL, "run %d: batches hold 2D runs only", r);
+        bool same = c.precision == c0.precision && c.nspecies == c0.nspecies && c.flags == c0.flags &&
+                    c.deposit_acc == c0.deposit_acc && Rs[r].slack == Rs[0].slack;
+        for (int s = 0; s < c.nspecies && same; ++s)
+            same = c.sp[s].Z == c0.sp[s].Z && c.sp[s].mu == c0.sp[s].mu && c.sp[s].a == c0.sp[s].a;
+        if (!same)
+            return fail(PIC_EINVAL, "run %d: precision, species, flags, deposit_acc and slack must match run 0", r);
+    }
+    return Status{};
+}
+
+Status batch_build(const std::vector<Resolved>& Rs, const pic_state* inits, const pic_allocator* alloc,
+                   hipStream_t stream, std::unique_ptr<BatchBase>& out) {
+    if (Rs[0].cfg.precision == PIC_FP64) {
+        auto* e = new BatchEngine<double>(alloc, stream);
+        out.reset(e);
+        return e->init(Rs, inits);
+    }
+    auto* e = new BatchEngine<float>(alloc, stream);
+    out.reset(e);
+    return e->init(Rs, inits);
+}
+
+int batch_finish(pic_batch* b, const Status& s) {
+    if (s.code != PIC_OK) {
+        b->err = s.msg;
+        if (s.code == PIC_EHIP || s.code == PIC_ESTATE) b->failed = true;
+    }
+    return s.code;
+}
+
+}  // namespace
+
+#define BATCH_CHECK(b)                                        \
+    do {                                                      \
+        if (!(b)) return PIC_ESTATE;                          \
+        if ((b)->failed || !(b)->eng) {                       \
+            (b)->err = "batch is unusable after an error";    \
+            return PIC_ESTATE;                                \
+        }                                                     \
+    } while (0)
+
+extern "C" {
+
+int pic_batch_init(int32_t nrun, const pic_config* cfgs, const pic_state* inits, int32_t autotune,
+                   const pic_allocator* alloc, void* hip_stream, pic_batch** out) {
+    g_init_error.clear();
+    if (!out) {
+        g_init_error = "out is NULL";
+        return PIC_EINVAL;
+    }
+    *out = nullptr;
+    if (nrun < 1 || nrun > 65535 || !cfgs || !inits) {
+        g_init_error = "need 1 <= nrun <= 65535 (runs are a grid dimension of the field update) and non-NULL cfgs and inits";
+        return PIC_EINVAL;
+    }
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        g_init_error = "allocator needs both alloc and free";
+        return PIC_EINVAL;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    std::vector<Resolved> Rs;
+    Status S = batch_resolve(nrun, cfgs, inits, Rs);
+    if (S.code) {
+        g_init_error = S.msg;
+        return S.code;
+    }
+    auto* b = new pic_batch();
+    const int ncand = (int)(sizeof kTileCandidates / sizeof kTileCandidates[0]);
+    std::vector<int> tunable;
+    for (int r = 0; r < nrun; ++r)
+        if (autotune && cfgs[r].tile[0] == 0 && cfgs[r].tile[1] == 0) tunable.push_back(r);
+    if (!tunable.empty()) {
+        // Autotune: build the batch with each candidate tile for the tunable
+        // runs, time two steps of each run's tiles, keep each run's fastest.
+        b->cands.assign(kTileCandidates, kTileCandidates + ncand);
+        b->tune.assign((size_t)nrun * ncand, 0.0);
+        std::vector<double> best(nrun, 1e300);
+        std::vector<int> best_t(nrun, 16);
+        for (int ci = 0; ci < ncand; ++ci) {
+            // a run that cannot take this candidate (shared memory) keeps the
+            // default tile in this trial and records no time for it
+            std::vector<pic_config> cc(cfgs, cfgs + nrun);
+            std::vector<char> tried(nrun, 0);
+            for (int r : tunable) {
+                cc[r].tile[0] = kTileCandidates[ci];
+                cc[r].tile[1] = kTileCandidates[ci];
+                Resolved one;
+                if (resolve_config(&cc[r], &inits[r], one).code) {
+                    cc[r].tile[0] = 0;
+                    cc[r].tile[1] = 0;
+                } else {
+                    tried[r] = 1;
+                }
+            }
+            std::vector<Resolved> Rc;
+            if (batch_resolve(nrun, cc.data(), inits, Rc).code) continue;
+            std::unique_ptr<BatchBase> e;
+            if (batch_build(Rc, inits, alloc, stream, e).code) continue;
+            std::vector<double> ns(nrun, 0.0);
+            if (e->step(1).code || e->run_time(true, nullptr).code || e->step(2).code ||
+                e->run_time(false, ns.data()).code)
+                continue;
+            for (int r : tunable) {
+                if (!tried[r]) continue;
+                int64_t info[4];
+                e->run_info(r, info);
+                const double t = ns[r] / (2.0 * (double)std::max<int64_t>(info[2], 1));
+                b->tune[(size_t)r * ncand + ci] = t;
+                if (t < best[r]) {
+                    best[r] = t;
+                    best_t[r] = kTileCandidates[ci];
+                }
+            }
+        }
+        std::vector<pic_config> cc(cfgs, cfgs + nrun);
+        for (int r : tunable) {
+            cc[r].tile[0] = best_t[r];
+            cc[r].tile[1] = best_t[r];
+        }
+        S = batch_resolve(nrun, cc.data(), inits, Rs);
+        if (S.code) {
+            g_init_error = S.msg;
+            delete b;
+            return S.code;
+        }
+    }
+    S = batch_build(Rs, inits, alloc, stream, b->eng);
+    if (S.code) {
+        g_init_error = S.msg;
+        delete b;
+        return S.code;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch* b, int32_t nsteps) {
+    BATCH_CHECK(b);
+    if (nsteps < 0) {
+        b->err = "nsteps must be >= 0";
+        return PIC_EINVAL;
+    }
+    return batch_finish(b, b->eng->step(nsteps));
+}
+
+int pic_batch_polarization(pic_batch* b, int32_t run, int32_t species, double emin, double emax,
+                           double P_out[3], int64_t* N_out) {
+    BATCH_CHECK(b);
+    if (!P_out || !N_out) {
+        b->err = "P_out and N_out must not be NULL";
+        return PIC_EINVAL;
+    }
+    return batch_finish(b, b->eng->polarization(run, species, emin, emax, P_out, N_out));
+}
+
+int pic_batch_fields(pic_batch* b, int32_t run, uint32_t mask, double* host_out, size_t cap_doubles) {
+    BATCH_CHECK(b);
+    return batch_finish(b, b->eng->fields(run, mask, host_out, cap_doubles));
+}
+
+int pic_batch_particles(pic_batch* b, int32_t run, int32_t species, double* host_out, size_t cap_doubles,
+                        int64_t* n_out) {
+    BATCH_CHECK(b);
+    return batch_finish(b, b->eng->particles(run, species, host_out, cap_doubles, n_out));
+}
+
+int pic_batch_info(pic_batch* b, int32_t run, int64_t out[4]) {
+    BATCH_CHECK(b);
+    if (!out || run < 0 || run >= b->eng->nruns()) {
+        b->err = "run out of range or out is NULL";
+        return PIC_EINVAL;
+    }
+    b->eng->run_info(run, out);
+    return PIC_OK;
+}
+
+int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, int32_t cap_cand, int32_t* ncand_out) {
+    BATCH_CHECK(b);
+    const int nc = (int)b->cands.size();
+    if (ncand_out) *ncand_out = nc;
+    if (nc == 0) return PIC_OK;
+    if (cap_cand < nc || !cand_out || !ns_out) {
+        b->err = "cap_cand too small or NULL output";
+        return PIC_EINVAL;
+    }
+    for (int i = 0; i < nc; ++i) cand_out[i] = b->cands[i];
+    std::copy(b->tune.begin(), b->tune.end(), ns_out);
+    return PIC_OK;
+}
+
+int pic_batch_stats(pic_batch* b, int64_t* out, int32_t cap) {
+    BATCH_CHECK(b);
+    return batch_finish(b, b->eng->stats(out, cap));
+}
+
+int pic_batch_timing(pic_batch* b, int32_t enable) {
+    BATCH_CHECK(b);
+    return batch_finish(b, b->eng->timing(enable));
+}
+
+int pic_batch_timing_read(pic_batch* b, double* ms_out, int64_t* launches_out, int32_t cap) {
+    BATCH_CHECK(b);
+    return batch_finish(b, b->eng->timing_read(ms_out, launches_out, cap));
+}
+
+const char* pic_batch_last_error(const pic_batch* b) {
+    if (!b) return g_init_error.c_str();
+    return b->err.c_str();
+}
+
+void pic_batch_free(pic_batch* b) {
+    delete b;
 }
 
 }  // extern "C"

@@ -11,13 +11,8 @@ constexpr int kFx = 64, kFy = 4;   // field kernels: 64 x 4 threads, x fastest
 // B_z at (i+1/2, j+1/2, k); E_a at half a cell along a.  Forward differences
 // with periodic wrap.  In 2D every d/dz is zero.
 template <typename real, int DIM>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_b(Geom g, Consts<real> k, Fields<real> f) {
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    const int kz = blockIdx.z;
+__device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, int i, int j, int kz) {
     const int nx = g.n[0], ny = g.n[1];
-    if (i >= nx || j >= ny) return;
     const long long nxy = (long long)nx * ny;
     const long long c = kz * nxy + (long long)j * nx + i;
     const long long ip = i + 1 == nx ? c - i : c + 1;
@@ -39,6 +34,15 @@ k_fdtd_b(Geom g, Consts<real> k, Fields<real> f) {
     f.B[2][c] -= cz;
 }
 
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_b(Geom g, Consts<real> k, Fields<real> f) {
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    fdtd_b_at<real, DIM>(g, k, f, i, j, blockIdx.z);
+}
+
 // E += dt (curl B - J).  Backward differences with periodic wrap.  The
 // other current buffer, no longer needed, is zeroed here for the next
 // step's deposit (when jclear is non-NULL).
@@ -47,13 +51,9 @@ struct JClear {
 };
 
 template <typename real, int DIM>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    const int kz = blockIdx.z;
+__device__ inline void fdtd_e_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, const JClear& jclear,
+                                 int i, int j, int kz) {
     const int nx = g.n[0], ny = g.n[1];
-    if (i >= nx || j >= ny) return;
     const long long nxy = (long long)nx * ny;
     const long long c = kz * nxy + (long long)j * nx + i;
     const long long im = i == 0 ? c + nx - 1 : c - 1;
@@ -78,6 +78,51 @@ k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
         static_cast<real*>(jclear.c[1])[c] = real(0);
         static_cast<real*>(jclear.c[2])[c] = real(0);
     }
+}
+
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    fdtd_e_at<real, DIM>(g, k, f, jclear, i, j, blockIdx.z);
+}
+
+// Batches of 2D runs: run blockIdx.z, its cells at its offset.
+template <typename real>
+__device__ inline Fields<freal> offset_fields(const Fields<freal>& f, long long off) {
+    Fields<freal> r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        r.E[c] = f.E[c] + off;
+        r.B[c] = f.B[c] + off;
+        r.J[c] = f.J[c] + off;
+    }
+    return r;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_b_batch(const RunDesc<real>* __restrict__ runs, Fields<freal> f) {
+    const RunDesc<real>& rd = runs[blockIdx.z];
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    if (i >= rd.g.n[0] || j >= rd.g.n[1]) return;
+    fdtd_b_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), i, j, 0);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kFx * kFy)
+k_fdtd_e_batch(const RunDesc<real>* __restrict__ runs, Fields<freal> f, JClear jclear) {
+    const RunDesc<real>& rd = runs[blockIdx.z];
+    const int i = blockIdx.x * kFx + threadIdx.x;
+    const int j = blockIdx.y * kFy + threadIdx.y;
+    if (i >= rd.g.n[0] || j >= rd.g.n[1]) return;
+    JClear jc = jclear;
+    if (jc.c[0])
+        for (int a = 0; a < 3; ++a) jc.c[a] = static_cast<freal*>(jc.c[a]) + rd.cell_off;
+    fdtd_e_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), jc, i, j, 0);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -170,8 +215,11 @@ k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st
     } else {
         const int n = ctr[CTR_STASH];
         const int b = blockIdx.x - nseg, nb = gridDim.x - nseg;
-        for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock)
-            reduce_one<real, DIM>(mode, st, i, st.sp[i], g, ra, v, rho);
+        for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+            const int tag = st.sp[i];   // run * kMaxSpecies + species
+            if (tag / kMaxSpecies != ra.run) continue;
+            reduce_one<real, DIM>(mode, st, i, tag % kMaxSpecies, g, ra, v, rho);
+        }
     }
     if (mode != RED_RHO) block_sum_add<4>(v, acc);
 }
@@ -367,6 +415,34 @@ hipError_t launch_bin_particles(const Geom& g, const PArrays<real>& p, const Seg
                        seg, st, ctr, ba, out);
     return hipGetLastError();
 }
+
+template <typename real>
+hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+                               const Fields<freal>& f, hipStream_t stream) {
+    const dim3 grid((nx_max + kFx - 1) / kFx, (ny_max + kFy - 1) / kFy, nruns);
+    hipLaunchKernelGGL((k_fdtd_b_batch<real>), grid, dim3(kFx, kFy), 0, stream, runs, f);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+                               const Fields<freal>& f, freal* const* jclear, hipStream_t stream) {
+    JClear jc{{nullptr, nullptr, nullptr}};
+    if (jclear)
+        for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
+    const dim3 grid((nx_max + kFx - 1) / kFx, (ny_max + kFy - 1) / kFy, nruns);
+    hipLaunchKernelGGL((k_fdtd_e_batch<real>), grid, dim3(kFx, kFy), 0, stream, runs, f, jc);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fdtd_b_batch<float>(const RunDesc<float>*, int, int, int, const Fields<freal>&,
+                                               hipStream_t);
+template hipError_t launch_fdtd_b_batch<double>(const RunDesc<double>*, int, int, int, const Fields<freal>&,
+                                                hipStream_t);
+template hipError_t launch_fdtd_e_batch<float>(const RunDesc<float>*, int, int, int, const Fields<freal>&,
+                                               freal* const*, hipStream_t);
+template hipError_t launch_fdtd_e_batch<double>(const RunDesc<double>*, int, int, int, const Fields<freal>&,
+                                                freal* const*, hipStream_t);
 
 template <typename real>
 hipError_t launch_field_energy(const Geom& g, const Fields<real>& f, double* acc,

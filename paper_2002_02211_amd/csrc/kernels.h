@@ -30,6 +30,50 @@ hipError_t launch_repack_segments(const PArrays<real>& from, const PArrays<real>
                                   const int32_t* old_start, const int32_t* new_start,
                                   const int32_t* count, int nseg, int ndim, hipStream_t stream);
 
+// ---- batches of independent 2D runs in shared stores
+// Run r's fields start at cell cell_off of the concatenated field arrays, its
+// segments at sid_base and its tiles at tile_base; its leavers and overflow
+// particles carry r * kMaxSpecies + species in the species word.
+template <typename real>
+struct RunDesc {
+    Geom g;
+    Consts<real> k;      // particle constants (push precision)
+    Consts<freal> kf;    // field-update constants
+    long long cell_off;
+    int sid_base;
+    int tile_base;
+};
+
+struct TileRef {
+    int run;
+    int t;   // tile index within the run
+};
+
+// Persistent push: blocks workgroups take tiles from order[0 .. ntiles) in
+// turn; run_ns (nruns counters, may be NULL) accumulates each run's tile time.
+template <typename real, typename acc_t>
+hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, int ntiles, int blocks,
+                                   size_t lds, const PArrays<real>& p, const Segs& seg, const PArrays<real>& lv,
+                                   int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
+                                   unsigned long long* run_ns, hipStream_t stream);
+// Workgroups of the batched push that fit on one CU with lds bytes of shared memory.
+template <typename real, typename acc_t>
+int push_batch_blocks_per_cu(size_t lds);
+template <typename real>
+hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, const int32_t* ctr,
+                                   const Fields<freal>& f, int deposit, int blocks, hipStream_t stream);
+template <typename real>
+hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p, const Segs& seg,
+                               const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
+                               unsigned long long* moved, int blocks, hipStream_t stream);
+// Field update of every run: grid (ceil(nx_max / 64), ceil(ny_max / 4), nruns).
+template <typename real>
+hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+                               const Fields<freal>& f, hipStream_t stream);
+template <typename real>
+hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+                               const Fields<freal>& f, freal* const* jclear, hipStream_t stream);
+
 // Yee update: B -= (dt/2) curl E, or E += dt (curl B - J) while zeroing the
 // three current arrays jclear (may be NULL).
 template <typename real, int DIM>
@@ -45,6 +89,7 @@ hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real
 //   rho:          rho (ncells doubles) += CIC charge Z w on the nodes (one
 //                 species, or all with species = -1).
 struct ReduceArgs {
+    int run;                // overflow-store particles of this run only (0 outside batches)
     int species;            // -1 = all
     double emin, emax;      // MeV window [emin, emax)
     double mu[kMaxSpecies];

@@ -99,21 +99,16 @@ __device__ inline void copy_particle(const PArrays<real>& from, long long i, con
 // the end.  Particles that stay in the tile are written back in place; those
 // that leave are appended to the leaver store, and the tile closes the holes
 // they leave before it finishes.
+// One tile: every particle of every species.  g, k and f are those of the
+// run the tile belongs to; its segments are sid_base + t nsp + sp, and its
+// leavers carry inst_tag + sp in the leaver store's species word.  Every
+// thread of the workgroup must call it.
 template <typename real, typename acc_t, int DIM>
-__global__ void __launch_bounds__(kBlock)
-k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
-             int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
+__device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
+                          const PArrays<real>& lv, int32_t* __restrict__ ctr, int slot, const Fields<freal>& f,
+                          int deposit, int t, int sid_base, int inst_tag) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_nleave, s_lbase;
-
-    // the other step's leaver counter is free again: clear it for the next step
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
-
-    // consecutive tiles go to the same XCD (workgroups are dealt round-robin
-    // over the 8 XCDs), so neighbours share guard cells in one L2
-    const int per = (g.ntiles + 7) >> 3;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (t >= g.ntiles) return;
     int tc[3];
     tc[0] = t % g.nt[0];
     tc[1] = (t / g.nt[0]) % g.nt[1];
@@ -191,7 +186,7 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     const uint32_t dummy_r = (uint32_t)(seg.dummy + lane) * (uint32_t)sizeof(real);
 
     for (int sp = 0; sp < g.nsp; ++sp) {
-        const int sid = t * g.nsp + sp;
+        const int sid = sid_base + t * g.nsp + sp;
         const int start = __builtin_amdgcn_readfirstlane(seg.start[sid]);
         const int n = __builtin_amdgcn_readfirstlane(seg.count[sid]);
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
@@ -360,7 +355,7 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
                         // the leaver is read before its slot is refilled (same thread)
                         if (r0 == 0) {
                             copy_particle(p, (long long)start + h, lv, (long long)lbase + rank, DIM);
-                            lv.sp[lbase + rank] = sp;
+                            lv.sp[lbase + rank] = inst_tag + sp;
                         }
                         if (h < nn && rank >= r0 && rank < r0 + kPairCap)
                             copy_particle(p, (long long)start + srcpos[rank - r0], p, (long long)start + h, DIM);
@@ -397,13 +392,27 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     }
 }
 
+template <typename real, typename acc_t, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
+             int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
+    // the other step's leaver counter is free again: clear it for the next step
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
+    // consecutive tiles go to the same XCD (workgroups are dealt round-robin
+    // over the 8 XCDs), so neighbours share guard cells in one L2
+    const int per = (g.ntiles + 7) >> 3;
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (t >= g.ntiles) return;
+    push_tile<real, acc_t, DIM>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0);
+}
+
 // Particles in the overflow store (tiles that ran out of slots): the same
 // step, gathering from and depositing into global memory directly.
+// One particle of the overflow store (species sp): gather from and deposit
+// into the global fields of its run.
 template <typename real, int DIM>
-__global__ void __launch_bounds__(kBlock)
-k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict__ ctr,
-             Fields<freal> f, int deposit) {
-    const int n = ctr[CTR_STASH];
+__device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, const PArrays<real>& st, int i,
+                                      int sp, const Fields<freal>& f, int deposit) {
     GlobalFields<freal, DIM> GF;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -413,69 +422,75 @@ k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict
 #pragma unroll
     for (int a = 0; a < 3; ++a) GF.n[a] = g.n[a];
     const real half_dt = real(0.5) * k.dt;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int sp = st.sp[i];
-        int c[3];
-        unpack_cell<DIM>(st.cell[i], c[0], c[1], c[2]);
-        real o[3] = {real(0), real(0), real(0)}, u[3], s[3];
+    int c[3];
+    unpack_cell<DIM>(st.cell[i], c[0], c[1], c[2]);
+    real o[3] = {real(0), real(0), real(0)}, u[3], s[3];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) o[a] = st.off[a][i];
+    for (int a = 0; a < DIM; ++a) o[a] = st.off[a][i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = st.u[a][i];
+        s[a] = st.s[a][i];
+    }
+    const real wgt = st.w[i];
+    Stencil1<real> stc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        stc[a] = a < DIM ? stencil1(c[a], o[a]) : Stencil1<real>{0, real(0), 0, real(0)};
+    real E[3], B[3];
+    gather_all(GF, stc, E, B);
+    boris_tbmt(u, s, E, B, k.eps[sp], k.r[sp], k.a[sp], half_dt);
+    const real ig = real(1) / fsqrt(real(1) + dot3(u, u));
+    real o0[3];
+    int dc[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        o0[a] = o[a];
+        dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+    }
+    if (deposit) {
+        real S0[3][3], S1[3][3], q[3];
+        GlobalJ<freal, DIM> sink;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            u[a] = st.u[a][i];
-            s[a] = st.s[a][i];
+            sink.J[a] = f.J[a];
+            sink.n[a] = g.n[a];
+            sink.b[a] = 0;
         }
-        const real wgt = st.w[i];
-        Stencil1<real> stc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            stc[a] = a < DIM ? stencil1(c[a], o[a]) : Stencil1<real>{0, real(0), 0, real(0)};
-        real E[3], B[3];
-        gather_all(GF, stc, E, B);
-        boris_tbmt(u, s, E, B, k.eps[sp], k.r[sp], k.a[sp], half_dt);
-        const real ig = real(1) / fsqrt(real(1) + dot3(u, u));
-        real o0[3];
-        int dc[3] = {0, 0, 0};
+        const real Z = k.Z[sp];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            o0[a] = o[a];
-            dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+            sink.b[a] = c[a] + shape_pair(o0[a], o[a], dc[a], S0[a], S1[a]);
+            q[a] = -Z * wgt * k.d_dt[a];
         }
-        if (deposit) {
-            real S0[3][3], S1[3][3], q[3];
-            GlobalJ<freal, DIM> sink;
+        esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
+    }
+    int nc[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                sink.J[a] = f.J[a];
-                sink.n[a] = g.n[a];
-                sink.b[a] = 0;
-            }
-            const real Z = k.Z[sp];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                sink.b[a] = c[a] + shape_pair(o0[a], o[a], dc[a], S0[a], S1[a]);
-                q[a] = -Z * wgt * k.d_dt[a];
-            }
-            esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
-        }
-        int nc[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            nc[a] = c[a] + dc[a];
-            if (a < DIM) {
-                if (nc[a] < 0) nc[a] += g.n[a];
-                if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
-            }
-        }
-        st.cell[i] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) st.off[a][i] = o[a];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            st.u[a][i] = u[a];
-            st.s[a][i] = s[a];
+    for (int a = 0; a < 3; ++a) {
+        nc[a] = c[a] + dc[a];
+        if (a < DIM) {
+            if (nc[a] < 0) nc[a] += g.n[a];
+            if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
         }
     }
+    st.cell[i] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) st.off[a][i] = o[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st.u[a][i] = u[a];
+        st.s[a][i] = s[a];
+    }
+}
+
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict__ ctr,
+             Fields<freal> f, int deposit) {
+    const int n = ctr[CTR_STASH];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        push_stash_one<real, DIM>(g, k, st, i, st.sp[i], f, deposit);
 }
 
 // Every leaver takes a slot at the end of its new segment, or a slot in the
@@ -517,6 +532,94 @@ k_repack_segments(PArrays<real> from, PArrays<real> to, const int32_t* __restric
     for (int i = threadIdx.x; i < n; i += kBlock) copy_particle(from, a + i, to, b + i, ndim);
 }
 
+// ---------------------------------------------------------------- batches
+
+template <typename real>
+__device__ inline Fields<freal> run_fields(const Fields<freal>& f, long long off) {
+    Fields<freal> r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        r.E[c] = f.E[c] + off;
+        r.B[c] = f.B[c] + off;
+        r.J[c] = f.J[c] + off;
+    }
+    return r;
+}
+
+// Persistent push over the tiles of every run, largest tiles first: each
+// workgroup takes the next tile from a counter until none is left.  The
+// counter of the other step parity is cleared for the next step.
+template <typename real, typename acc_t>
+__global__ void __launch_bounds__(kBlock)
+k_push_tiles_batch(const RunDesc<real>* __restrict__ runs, const TileRef* __restrict__ order, int ntiles,
+                   PArrays<real> p, Segs seg, PArrays<real> lv, int32_t* __restrict__ ctr, int slot,
+                   Fields<freal> f, int deposit, unsigned long long* __restrict__ run_ns) {
+    __shared__ int s_item;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr[slot ^ 1] = 0;
+        ctr[CTR_QUEUE0 + (slot ^ 1)] = 0;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[CTR_QUEUE0 + slot], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= ntiles) break;
+        const TileRef tr = order[item];
+        const Geom g = runs[tr.run].g;
+        const Consts<real> k = runs[tr.run].k;
+        const Fields<freal> fr = run_fields<real>(f, runs[tr.run].cell_off);
+        const unsigned long long t0 = run_ns ? wall_clock64() : 0ull;
+        push_tile<real, acc_t, 2>(g, k, p, seg, lv, ctr, slot, fr, deposit, tr.t, runs[tr.run].sid_base,
+                                  tr.run * kMaxSpecies);
+        __syncthreads();   // shared memory is restaged for the next tile
+        if (run_ns && threadIdx.x == 0) atomicAdd(run_ns + tr.run, (wall_clock64() - t0) * 10ull);
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+k_push_stash_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> st, const int32_t* __restrict__ ctr,
+                   Fields<freal> f, int deposit) {
+    const int n = ctr[CTR_STASH];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int tag = st.sp[i];
+        const int run = tag / kMaxSpecies;
+        push_stash_one<real, 2>(runs[run].g, runs[run].k, st, i, tag - run * kMaxSpecies,
+                                run_fields<real>(f, runs[run].cell_off), deposit);
+    }
+}
+
+// The batch's leavers (the list [0, ctr[slot]) of the leaver store): each
+// takes a slot at the end of its new segment in its own run, or a slot in
+// the overflow store when that segment is full.
+template <typename real>
+__global__ void __launch_bounds__(kBlock)
+k_insert_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> p, Segs seg, PArrays<real> lv,
+               PArrays<real> st, int32_t* __restrict__ ctr, int slot, unsigned long long* __restrict__ moved) {
+    const int L = ctr[slot];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(moved, (unsigned long long)L);
+    for (int q = blockIdx.x * kBlock + threadIdx.x; q < L; q += gridDim.x * kBlock) {
+        const int tag = lv.sp[q];
+        const int run = tag / kMaxSpecies;
+        const int sp = tag - run * kMaxSpecies;
+        const Geom g = runs[run].g;
+        int c[3];
+        unpack_cell<2>(lv.cell[q], c[0], c[1], c[2]);
+        const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1]);
+        const int sid = runs[run].sid_base + tile * g.nsp + sp;
+        const int pos = atomicAdd(&seg.count[sid], 1);
+        if (pos < seg.cap[sid]) {
+            copy_particle(lv, q, p, (long long)seg.start[sid] + pos, 2);
+        } else {
+            atomicSub(&seg.count[sid], 1);
+            const int j = atomicAdd(&ctr[CTR_STASH], 1);
+            copy_particle(lv, q, st, j, 2);
+            st.sp[j] = tag;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <typename real>
@@ -556,6 +659,62 @@ hipError_t launch_insert(const Geom& g, const PArrays<real>& p, const Segs& seg,
                        g, p, seg, lv, st, ctr, slot, moved);
     return hipGetLastError();
 }
+
+template <typename real, typename acc_t>
+hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, int ntiles, int blocks,
+                                   size_t lds, const PArrays<real>& p, const Segs& seg, const PArrays<real>& lv,
+                                   int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
+                                   unsigned long long* run_ns, hipStream_t stream) {
+    hipLaunchKernelGGL((k_push_tiles_batch<real, acc_t>), dim3(blocks), dim3(kBlock), lds, stream, runs, order,
+                       ntiles, p, seg, lv, ctr, slot, f, deposit, run_ns);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, const int32_t* ctr,
+                                   const Fields<freal>& f, int deposit, int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL((k_push_stash_batch<real>), dim3(blocks), dim3(kBlock), 0, stream, runs, st, ctr, f,
+                       deposit);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p, const Segs& seg,
+                               const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
+                               unsigned long long* moved, int blocks, hipStream_t stream) {
+    hipLaunchKernelGGL((k_insert_batch<real>), dim3(blocks), dim3(kBlock), 0, stream, runs, p, seg, lv, st, ctr,
+                       slot, moved);
+    return hipGetLastError();
+}
+
+template hipError_t launch_push_tiles_batch<float, double>(const RunDesc<float>*, const TileRef*, int, int,
+    size_t, const PArrays<float>&, const Segs&, const PArrays<float>&, int32_t*, int, const Fields<freal>&, int,
+    unsigned long long*, hipStream_t);
+template hipError_t launch_push_tiles_batch<float, float>(const RunDesc<float>*, const TileRef*, int, int,
+    size_t, const PArrays<float>&, const Segs&, const PArrays<float>&, int32_t*, int, const Fields<freal>&, int,
+    unsigned long long*, hipStream_t);
+template hipError_t launch_push_tiles_batch<double, double>(const RunDesc<double>*, const TileRef*, int, int,
+    size_t, const PArrays<double>&, const Segs&, const PArrays<double>&, int32_t*, int, const Fields<freal>&,
+    int, unsigned long long*, hipStream_t);
+template hipError_t launch_push_stash_batch<float>(const RunDesc<float>*, const PArrays<float>&, const int32_t*,
+    const Fields<freal>&, int, int, hipStream_t);
+template hipError_t launch_push_stash_batch<double>(const RunDesc<double>*, const PArrays<double>&,
+    const int32_t*, const Fields<freal>&, int, int, hipStream_t);
+template hipError_t launch_insert_batch<float>(const RunDesc<float>*, const PArrays<float>&, const Segs&,
+    const PArrays<float>&, const PArrays<float>&, int32_t*, int, unsigned long long*, int, hipStream_t);
+template hipError_t launch_insert_batch<double>(const RunDesc<double>*, const PArrays<double>&, const Segs&,
+    const PArrays<double>&, const PArrays<double>&, int32_t*, int, unsigned long long*, int, hipStream_t);
+
+template <typename real, typename acc_t>
+int push_batch_blocks_per_cu(size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_push_tiles_batch<real, acc_t>, kBlock, lds) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+template int push_batch_blocks_per_cu<float, double>(size_t);
+template int push_batch_blocks_per_cu<float, float>(size_t);
+template int push_batch_blocks_per_cu<double, double>(size_t);
 
 #define SPINPIC_INST_PUSH(real, acc, DIM)                                                       \
     template hipError_t launch_push_tiles<real, acc, DIM>(const Geom&, const Consts<real>&,    \

@@ -28,6 +28,9 @@ FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
             "pic_spectrum", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
             "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
+            "pic_batch_init", "pic_batch_step", "pic_batch_polarization", "pic_batch_fields",
+            "pic_batch_particles", "pic_batch_info", "pic_batch_tuning", "pic_batch_stats",
+            "pic_batch_timing", "pic_batch_timing_read", "pic_batch_last_error", "pic_batch_free",
             "pic_track_create", "pic_track_forward", "pic_track_backward", "pic_track_timing",
             "pic_track_last_error", "pic_track_free")
 
@@ -113,6 +116,23 @@ def load_library(path=LIB_PATH):
     lib.pic_timing.argtypes = [P, ctypes.c_int32]
     lib.pic_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    I32 = ctypes.POINTER(ctypes.c_int32)
+    lib.pic_batch_init.argtypes = [ctypes.c_int32, ctypes.POINTER(Config), ctypes.POINTER(State), ctypes.c_int32,
+                                   ctypes.POINTER(Allocator), P, ctypes.POINTER(P)]
+    lib.pic_batch_step.argtypes = [P, ctypes.c_int32]
+    lib.pic_batch_polarization.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, D, I64]
+    lib.pic_batch_fields.argtypes = [P, ctypes.c_int32, ctypes.c_uint32, D, ctypes.c_size_t]
+    lib.pic_batch_particles.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_size_t, I64]
+    lib.pic_batch_info.argtypes = [P, ctypes.c_int32, I64]
+    lib.pic_batch_tuning.argtypes = [P, I32, D, ctypes.c_int32, I32]
+    lib.pic_batch_stats.argtypes = [P, I64, ctypes.c_int32]
+    lib.pic_batch_timing.argtypes = [P, ctypes.c_int32]
+    lib.pic_batch_timing_read.argtypes = [P, D, I64, ctypes.c_int32]
+    lib.pic_batch_last_error.argtypes = [P]
+    lib.pic_batch_last_error.restype = ctypes.c_char_p
+    lib.pic_batch_free.argtypes = [P]
+    lib.pic_batch_free.restype = None
     lib.pic_track_create.argtypes = [ctypes.POINTER(TrackConfig), ctypes.c_int64,
                                      ctypes.POINTER(Allocator), P, ctypes.POINTER(P)]
     lib.pic_track_forward.argtypes = [P, ctypes.c_double, ctypes.c_double, D, D, D, D, D, D, D]
@@ -127,7 +147,8 @@ def load_library(path=LIB_PATH):
     lib.pic_free.argtypes = [P]
     lib.pic_free.restype = None
     for name in EXPORTED:
-        if name not in ("pic_last_error", "pic_free", "pic_track_last_error", "pic_track_free"):
+        if name not in ("pic_last_error", "pic_free", "pic_track_last_error", "pic_track_free",
+                        "pic_batch_last_error", "pic_batch_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -215,13 +236,9 @@ class _TorchMemory:
 
 # ---------------------------------------------------------------- C calls
 
-def pic_init(cfg, particles, fields=None, device=0, memory=None):
-    """Create a context.  particles: list of (N, 10) float64 arrays per species
-    (x y z ux uy uz sx sy sz w); fields: (6, nz, ny, nx) float64 or None.
-    Returns (ctx, memory) - keep ``memory`` alive as long as the context."""
-    lib = load_library()
+def _make_state(particles, fields, keep):
+    """A State pointing at float64 copies of the arrays (kept alive in keep)."""
     st = State()
-    keep = []
     for s in range(MAX_SPECIES):
         if s < len(particles) and particles[s] is not None and len(particles[s]):
             arr = np.ascontiguousarray(particles[s], dtype=np.float64)
@@ -237,6 +254,16 @@ def pic_init(cfg, particles, fields=None, device=0, memory=None):
         F = np.ascontiguousarray(fields, dtype=np.float64)
         keep.append(F)
         st.fields = F.ctypes.data
+    return st
+
+
+def pic_init(cfg, particles, fields=None, device=0, memory=None):
+    """Create a context.  particles: list of (N, 10) float64 arrays per species
+    (x y z ux uy uz sx sy sz w); fields: (6, nz, ny, nx) float64 or None.
+    Returns (ctx, memory) - keep ``memory`` alive as long as the context."""
+    lib = load_library()
+    keep = []
+    st = _make_state(particles, fields, keep)
     if memory is None:
         memory = _TorchMemory(device)
     ctx = ctypes.c_void_p()
@@ -496,3 +523,102 @@ def wake_polarization(tracker, E0, kp, x0, u0, s0):
                     torch.from_numpy(gs).to(dv[4]))
 
     return _Fn.apply(E0, kp, x0, u0, s0)
+
+
+# ---------------------------------------------------------------- batches
+
+def _batch_check(code, b):
+    if code != PIC_OK:
+        msg = load_library().pic_batch_last_error(b)
+        raise PicError(code, msg.decode() if msg else "")
+
+
+class Batch:
+    """Independent 2D runs stepped together (pic_batch_*).  cfgs: list of
+    Config; states: list of (particles, fields) as for Simulation."""
+
+    def __init__(self, cfgs, states, autotune=False, device=0):
+        lib = load_library()
+        n = len(cfgs)
+        self.nruns = n
+        self.cfgs = list(cfgs)
+        carr = (Config * n)(*cfgs)
+        keep = []
+        sarr = (State * n)(*[_make_state(p, f, keep) for p, f in states])
+        self.counts = [[len(p) if p is not None else 0 for p in parts] for parts, _ in states]
+        self._mem = _TorchMemory(device)
+        h = ctypes.c_void_p()
+        _batch_check(lib.pic_batch_init(n, carr, sarr, 1 if autotune else 0, ctypes.byref(self._mem.allocator),
+                                        self._mem.stream_handle, ctypes.byref(h)), None)
+        self.h = h
+
+    def step(self, n=1):
+        _batch_check(load_library().pic_batch_step(self.h, int(n)), self.h)
+
+    def polarization(self, run, species=-1, emin=-math.inf, emax=math.inf):
+        P = np.zeros(3)
+        N = ctypes.c_int64()
+        _batch_check(load_library().pic_batch_polarization(self.h, int(run), int(species), float(emin), float(emax),
+                                                           _dptr(P), ctypes.byref(N)), self.h)
+        return P, int(N.value)
+
+    def fields(self, run, names=FIELD_NAMES[:9]):
+        c = self.cfgs[run]
+        shape = (1, c.n[1], c.n[0])
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_NAMES.index(nm)
+        order = [nm for nm in FIELD_NAMES if nm in names]
+        out = np.empty(len(order) * shape[1] * shape[2])
+        _batch_check(load_library().pic_batch_fields(self.h, int(run), mask, _dptr(out), out.size), self.h)
+        arr = out.reshape((len(order),) + shape)
+        return {nm: arr[i] for i, nm in enumerate(order)}
+
+    def particles(self, run, species):
+        count = self.counts[run][species]
+        out = np.empty((count, 11))
+        n = ctypes.c_int64()
+        _batch_check(load_library().pic_batch_particles(self.h, int(run), int(species), _dptr(out), out.size,
+                                                        ctypes.byref(n)), self.h)
+        return out[: n.value]
+
+    def info(self, run):
+        out = (ctypes.c_int64 * 4)()
+        _batch_check(load_library().pic_batch_info(self.h, int(run), out), self.h)
+        return {"tile": (out[0], out[1]), "particles": out[2], "cells": out[3]}
+
+    def tuning(self):
+        """(candidate tile edges, (nruns, ncand) ns per particle-step) or None."""
+        nc = ctypes.c_int32()
+        cands = (ctypes.c_int32 * 16)()
+        ns = np.zeros(self.nruns * 16)
+        _batch_check(load_library().pic_batch_tuning(self.h, cands, _dptr(ns), 16, ctypes.byref(nc)), self.h)
+        if nc.value == 0:
+            return None
+        return list(cands[: nc.value]), ns[: self.nruns * nc.value].reshape(self.nruns, nc.value)
+
+    def stats(self):
+        out = (ctypes.c_int64 * 7)()
+        _batch_check(load_library().pic_batch_stats(self.h, out, 7), self.h)
+        return {"steps": out[0], "moved": out[1], "overflow": out[2], "repacks": out[3],
+                "particles": out[4], "push_workgroups": out[5], "tiles": out[6]}
+
+    def timing(self, enable=True):
+        _batch_check(load_library().pic_batch_timing(self.h, 1 if enable else 0), self.h)
+
+    def timing_read(self):
+        ms = np.zeros(4)
+        n = (ctypes.c_int64 * 4)()
+        _batch_check(load_library().pic_batch_timing_read(self.h, _dptr(ms), n, 4), self.h)
+        return {nm: (ms[i], n[i]) for i, nm in enumerate(TIMER_NAMES)}
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load_library().pic_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # noqa: BLE001
+            pass

@@ -10,5 +10,5 @@ from .workloads import (  # noqa: F401
     LAMBDA, ME_C2_MEV, MP_OVER_ME, A_E, A_P,
     electron, proton, courant_dt, preset, PRESETS,
     make_particles, make_laser_fields, make_state, grid_shape,
-    MICRON, tracking_preset, make_beam,
+    MICRON, tracking_preset, make_beam, batch_specs,
 )

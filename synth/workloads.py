@@ -279,3 +279,49 @@ def make_beam(spec):
     u[:, 2] = np.sqrt(gamma * gamma - 1.0)
     s = np.tile(np.asarray(spec["s0"], dtype=np.float64), (n, 1))
     return x, u, s
+
+
+# ---------------------------------------------------------------- batches of runs
+
+def batch_specs(name="c5", **overrides):
+    """Recipes of a batch of independent 2D runs.
+
+    ``c5``: 64 runs, grids drawn uniformly from 128-1024 x 64-256 cells of
+    0.05 wavelengths, density log-uniform in 0.001-0.05 n_c (uniform in each
+    run), 2-8 particles per cell per species, linearly polarized a0 uniform in
+    1-10 with a waist of a quarter of the box height and a 10-wavelength
+    duration, centred a quarter into the box; 1 keV, spins +y, FP32, 300 steps.
+    ``batch_small``: five small runs of uneven size for parity tests (FP64)."""
+    seed = overrides.pop("seed", 5 if name == "c5" else 55)
+    rng = np.random.default_rng(seed)
+    specs = []
+    if name == "c5":
+        nrun = overrides.pop("nrun", 64)
+        for r in range(nrun):
+            nx = int(rng.integers(128, 1025))
+            ny = int(rng.integers(64, 257))
+            n0 = float(np.exp(rng.uniform(np.log(0.001), np.log(0.05))))
+            ppc = int(rng.integers(2, 9))
+            a0 = float(rng.uniform(1.0, 10.0))
+            specs.append(_batch_run("c5_%02d" % r, nx, ny, n0, ppc, a0, 1000 + r, "fp32"))
+    elif name == "batch_small":
+        shapes = [(48, 32, 2), (80, 40, 3), (64, 24, 1), (96, 48, 2), (32, 32, 4)]
+        for r, (nx, ny, ppc) in enumerate(shapes):
+            specs.append(_batch_run("small_%d" % r, nx, ny, 0.05, ppc, 2.0 + r, 2000 + r, "fp64",
+                                    T_keV=5.0, steps=20))
+    else:
+        raise KeyError(name)
+    for s in specs:
+        s.update(overrides)
+    return specs
+
+
+def _batch_run(name, nx, ny, n0, ppc, a0, seed, precision, T_keV=1.0, steps=300):
+    s = _base(name, 2, (nx, ny), (0.05, 0.05), steps, seed, precision, (0, 0, 1))
+    s["plasma"] = {"ppc": ppc, "profile": "uniform", "n0": n0, "ramp_len": 0.0,
+                   "noise": 0.0, "T_keV": T_keV, "s0": (0.0, 1.0, 0.0)}
+    Ly = ny * s["d"][1]
+    Lx = nx * s["d"][0]
+    s["laser"] = {"a0": a0, "waist": 0.25 * Ly, "duration": 10 * LAMBDA,
+                  "x_center": 0.25 * Lx, "pol": "lp"}
+    return s
