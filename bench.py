@@ -48,6 +48,9 @@ WORKLOAD_TEXT = {
           "0.005 n_c with 1% noise, 1 keV, CP a0=20 waist 6 lambda, spins +x",
     "c4": "differentiable spin tracking: 2^20 protons, analytic wake E0=0.1 kp=0.1, dt=0.5, 4000 steps, "
           "states kept every 100; final polarization and its gradient w.r.t. E0, kp and the initial phase space",
+    "c5": "64 independent 2D3V runs stepped together: grids uniform in 128-1024 x 64-256 cells of 0.05 lambda, "
+          "density log-uniform 0.001-0.05 n_c, 2-8 per cell per species (e+p, 56,090,560 particles, "
+          "6,061,794 cells), LP a0 uniform 1-10, 1 keV, spins +y; FP32 push, FP64 reductions, autotuned tiles",
 }
 
 # Algorithmic FP32 operations per particle-step of the tracking kernels
@@ -280,6 +283,158 @@ def bench_tracking(args):
     print(json.dumps(result), flush=True)
 
 
+def _time_batch(S, cfgs, states, autotune, warmup, steps):
+    """Build a batch, warm up, time `steps` steps; returns (batch, init s, elapsed s, timers)."""
+    import torch
+    t0 = time.time()
+    b = S.Batch(cfgs, states, autotune=autotune)
+    torch.cuda.synchronize()
+    t_init = time.time() - t0
+    print("[bench] batch init (autotune %s) %.1f s" % (autotune, t_init), file=sys.stderr, flush=True)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    b.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = b.timing_read()
+    b.timing(False)
+    print("[bench] batch (autotune %s) timed %d steps in %.3f s" % (autotune, steps, elapsed),
+          file=sys.stderr, flush=True)
+    return b, t_init, elapsed, timers
+
+
+def bench_batch(args):
+    """The c5 batch: all runs stepped together (autotuned tiles); beside it the
+    same batch with the default tile and the runs stepped one after another
+    by the single-run engine with the tiles the autotuner chose."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2002_02211_amd import spinpic as S
+    specs = synth.batch_specs("c5")
+    t0 = time.time()
+    states = [synth.make_state(s) for s in specs]
+    pairs = [(st["particles"], st["fields"]) for st in states]
+    npart = sum(sum(p.shape[0] for p in st["particles"]) for st in states)
+    ncells = sum(int(s["n"][0]) * int(s["n"][1]) for s in specs)
+    print("[bench] c5: %d runs, %d particles, %d cells generated in %.1f s"
+          % (len(specs), npart, ncells, time.time() - t0), file=sys.stderr, flush=True)
+    cfgs = [S.config_from_spec(s, precision="fp32") for s in specs]
+
+    b, t_init, elapsed, timers = _time_batch(S, cfgs, pairs, True, args.warmup, args.steps)
+    stats = b.stats()
+    tiles = [b.info(r)["tile"] for r in range(len(specs))]
+    tu = b.tuning()
+    pol = [b.polarization(r)[0].tolist() for r in range(len(specs))]
+    b.close()
+    del b
+    launch_bytes, per_particle, per_cell = algorithmic_bytes(2, "fp32", npart, ncells)
+    push_ms, push_n = timers["push_deposit"]
+    avg_push_s = push_ms / 1e3 / max(push_n, 1)
+    achieved = launch_bytes / avg_push_s / 1e9
+
+    result_extra = {}
+    if not args.batch_only:
+        result_extra = _batch_comparisons(S, specs, cfgs, pairs, tiles, launch_bytes, npart, args)
+    chosen = {}
+    for t in tiles:
+        key = "%dx%d" % t
+        chosen[key] = chosen.get(key, 0) + 1
+    result = {
+        "metric": METRIC,
+        "value": npart * args.steps / elapsed,
+        "unit": "pushes/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5: " + WORKLOAD_TEXT["c5"], "runs": len(specs), "particles": npart,
+                   "cells": ncells, "precision": "FP32 particles and push; FP64 fields, currents, reductions",
+                   "tiles_chosen": chosen, "push_workgroups": stats["push_workgroups"],
+                   "tiles_total": stats["tiles"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("c5", "fp32", launch_bytes),
+                     "kernel": "k_push_tiles_batch (persistent: gather+Boris+T-BMT+move+Esirkepov deposit "
+                               "over the tiles of all runs)",
+                     "bytes_per_launch": launch_bytes, "bytes_per_particle": per_particle,
+                     "bytes_per_cell": per_cell, "avg_launch_ms": avg_push_s * 1e3,
+                     "push_pushes_per_s": npart / avg_push_s},
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
+        "autotune": {"init_s": t_init, "candidates": tu["candidates"],
+                     "push_ms_uniform": np.round(tu["kernel_ms"], 4).tolist(),
+                     "push_ms_per_run_tiles": round(tu["mixed_ms"], 4),
+                     "share_ns_per_particle_step_median": np.median(tu["share_ns"], axis=0).round(4).tolist()},
+        "polarization_run0": pol[0],
+    }
+    result.update(result_extra)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_batch(specs, states, budget_s=15.0)
+    print(json.dumps(result), flush=True)
+
+
+def _batch_comparisons(S, specs, cfgs, pairs, tiles, launch_bytes, npart, args):
+    """The same batch with the default tile, and the runs one after another."""
+    import torch
+    b16, _, el16, tm16 = _time_batch(S, cfgs, pairs, False, args.warmup, args.steps)
+    b16.close()
+    del b16
+    t16 = tm16["push_deposit"][0] / 1e3 / max(tm16["push_deposit"][1], 1)
+
+    # one run after another, each with the tile the autotuner gave it
+    seq_elapsed, seq_push = 0.0, 0.0
+    for r, (s, (parts, fields)) in enumerate(zip(specs, pairs)):
+        cfg = S.config_from_spec(s, precision="fp32", tile=tiles[r] + (1,))
+        sim = S.Simulation(cfg, parts, fields)
+        sim.step(args.warmup)
+        sim.timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        seq_elapsed += time.perf_counter() - t1
+        seq_push += sim.timing_read()["push_deposit"][0] / 1e3
+        sim.close()
+    print("[bench] sequential runs: %.3f s" % seq_elapsed, file=sys.stderr, flush=True)
+    return {
+        "default_tile_batch": {"tile": [16, 16], "value": npart * args.steps / el16, "unit": "pushes/s",
+                               "ms_per_step": el16 / args.steps * 1e3, "push_avg_launch_ms": t16 * 1e3,
+                               "push_hbm_frac": launch_bytes / t16 / 1e9 / HBM_PEAK_GBS},
+        "sequential_runs": {"value": npart * args.steps / seq_elapsed, "unit": "pushes/s",
+                            "ms_per_step": seq_elapsed / args.steps * 1e3,
+                            "push_ms_per_step": seq_push / args.steps * 1e3,
+                            "what": "the %d runs stepped one after another by pic_step, autotuned tiles"
+                                    % len(specs)},
+    }
+
+
+def cpu_baseline_batch(specs, states, budget_s):
+    """The FP64 NumPy oracle, single-threaded, pushing whole runs of the batch
+    (in order) through one gather+push+spin+deposit pass until about budget_s
+    of CPU time is spent."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ.setdefault(var, "1")
+    import oracle
+    n, dt, runs = 0, 0.0, 0
+    for spec, state in zip(specs, states):
+        sim = oracle.Sim(spec, state)
+        t0 = time.perf_counter()
+        for k in range(len(spec["species"])):
+            m = sim.xi[k].shape[0]
+            for lo in range(0, m, sim.CHUNK):
+                sim.push_species(k, lo, min(m, lo + sim.CHUNK))
+        dt += time.perf_counter() - t0
+        n += sum(x.shape[0] for x in sim.xi)
+        runs += 1
+        del sim
+        if dt >= budget_s:
+            break
+    return {"value": n / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d runs of the batch whole (%d particles), one gather+push+spin+deposit "
+                      "pass each, FP64 NumPy, one thread of %s, %.1f s" % (runs, n, cpu_model(), dt)}
+
+
 def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None):
     """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
     import torch
@@ -309,7 +464,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT),
-                    help="c1-c3: PIC steps; c4: differentiable tracking (forward + adjoint per step)")
+                    help="c1-c3: PIC steps; c4: differentiable tracking (forward + adjoint per step); "
+                         "c5: a batch of 64 uneven runs")
     ap.add_argument("--precision", default=None, choices=("fp32", "fp64"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
@@ -324,15 +480,19 @@ def main():
                     help="write the push kernel's traffic record from rocprofv3 counter files and exit")
     ap.add_argument("--cpu-sample", type=int, default=8_000_000,
                     help="particles per species in the CPU-baseline sample")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="c5: time the autotuned batch only (no default-tile batch, no sequential runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration)")
     args = ap.parse_args()
 
     if args.traffic_from:
         import synth
-        spec = synth.preset(args.workload)
-        write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload,
-                      args.precision or spec["precision"])
+        if args.workload == "c5":
+            precision = "fp32"
+        else:
+            precision = args.precision or synth.preset(args.workload)["precision"]
+        write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload, precision)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -348,10 +508,24 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     S.load_library()
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     if args.workload == "c4":
         if args.steps == 100 and args.warmup == 10:
             args.steps, args.warmup = 5, 1
         bench_tracking(args)
+        return
+    if args.workload == "c5":
+        if args.steps == 100 and args.warmup == 10:
+            args.steps = 300
+        bench_batch(args)
         return
 
     spec = synth.preset(args.workload)
@@ -361,15 +535,6 @@ def main():
     npart = sum(p.shape[0] for p in state["particles"])
     print("[bench] %s: %d particles generated in %.1f s" % (args.workload, npart, time.time() - t0),
           file=sys.stderr, flush=True)
-
-    if args.copy_probe_mib:
-        nbytes = args.copy_probe_mib << 20
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None

@@ -219,12 +219,17 @@ void pic_free(pic_ctx* ctx);
 typedef struct pic_batch pic_batch;
 
 /* nrun runs (1..65535) from cfgs[r], inits[r] (as for pic_init; host memory,
- * copied).  All runs must be 2D with the same precision, species, flags, deposit_acc
- * and slack; grids, cell sizes, time steps, tiles and particles may differ.
- * With autotune != 0 every run whose cfg tile is 0 x 0 gets the square tile
- * (8, 12, 16, 24 or 32 cells, clipped to the grid, among those whose shared
- * memory fits) under which its particles were pushed fastest in two timed
- * steps of the batch built with each candidate; otherwise 16 x 16.  Errors as pic_init, with the run named in pic_batch_last_error. */
+ * copied).  All runs must be 2D with the same precision, species, flags,
+ * deposit_acc and slack; grids, cell sizes, time steps, tiles and particles
+ * may differ.  Runs whose cfg tile is 0 x 0 get 16 x 16, or with
+ * autotune != 0 a square tile of 8, 12, 16, 24 or 32 cells (clipped to the
+ * grid) chosen by timing the batch: first every such run at each candidate
+ * (the fastest push launch gives c*), then each run at the candidate not
+ * larger than c* under which its tiles took the smallest share of the
+ * launch; the per-run choice is kept only if its launch is faster than c*
+ * for all.  (The largest tile of a batch sets how many workgroups of the
+ * persistent push fit on a compute unit.)  Errors as pic_init, with the run
+ * named in pic_batch_last_error. */
 int pic_batch_init(int32_t nrun, const pic_config* cfgs, const pic_state* inits, int32_t autotune,
                    const pic_allocator* alloc, void* hip_stream, pic_batch** out);
 
@@ -243,11 +248,15 @@ int pic_batch_particles(pic_batch* b, int32_t run, int32_t species, double* host
 int pic_batch_info(pic_batch* b, int32_t run, int64_t out[4]);
 
 /* The autotuner's measurements: *ncand_out candidate tile edges into
- * cand_out (cap_cand >= *ncand_out), and ns_out[r * ncand + c] the push time
- * per particle-step of run r under candidate c (0 where not tried).
- * *ncand_out is 0 when nothing was tuned. */
-int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, int32_t cap_cand,
-                     int32_t* ncand_out);
+ * cand_out (cap_cand >= *ncand_out); ns_out[r * ncand + c] the push time
+ * per particle-step of run r under candidate c: the summed durations of its
+ * tiles over the number of workgroups of the persistent push, which run side
+ * by side (0 where not tried); kernel_ms_out[c] (ncand + 1 entries) the mean
+ * push launch with the tunable runs at candidate c, and kernel_ms_out[ncand]
+ * with the per-run choice (0 if every run chose c*).  *ncand_out is 0 when
+ * nothing was tuned. */
+int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, double* kernel_ms_out,
+                     int32_t cap_cand, int32_t* ncand_out);
 
 /* As pic_stats (out[5] workgroups of the persistent push, out[6] tiles of
  * all runs when cap >= 7), pic_timing and pic_timing_read. */

@@ -387,6 +387,48 @@ static long long seg_capacity(long long count, double slack) {
     return round_up((long long)std::ceil(count * (1.0 + slack)) + 32, 32);
 }
 
+// Overflow policy.  Every kStashCheck steps the step loop waits for its
+// stream, so that the pinned copy of the overflow count is current (the host
+// can otherwise run many steps ahead of the GPU), and folds the overflow
+// store back into the tiles when it holds more than npart / kStashFrac
+// particles, or any at all on a kStashPeriod boundary: overflow particles are
+// pushed from global memory at a fraction of the tile push's rate.
+constexpr int kStashCheck = 16;
+constexpr int kStashPeriod = 64;
+constexpr long long kStashFrac = 512;
+constexpr int kStashBlocks = 1024;
+// A segment that overflowed is usually in a region still being compressed
+// (a laser's ponderomotive front): the repack gives it kGrowSlack times the
+// slack and keeps room it was given while the count stays within that.
+constexpr double kGrowSlack = 3.0;
+
+static bool repack_due(long long nstep, long long nstash, long long npart) {
+    if (nstash <= 0) return false;
+    return nstep % kStashPeriod == 0 || nstash > std::max(1024LL, npart / kStashFrac);
+}
+
+// capmax: the largest segment the tile's shared memory holds; a count above
+// it fails the shared-memory check after the repack.
+static long long regrow_capacity(long long want, long long oldcap, double slack, long long capmax) {
+    const long long grown = seg_capacity(want, kGrowSlack * slack);
+    long long cp = want > oldcap ? grown : std::max(seg_capacity(want, slack), std::min(oldcap, grown));
+    if (cp > capmax) cp = std::max(capmax, round_up(want, 32));
+    return cp;
+}
+
+// Largest segment capacity (whole 64-slot chunks) for which lds(max_chunks)
+// stays within the 64 KiB a workgroup may allocate.
+template <typename F>
+static long long max_segment_slots(F lds) {
+    int lo = 0, hi = 1 << 22;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (lds(mid) <= 64 * 1024) lo = mid;
+        else hi = mid - 1;
+    }
+    return (long long)lo * 64;
+}
+
 template <typename real, int DIM>
 Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     R_ = R;
@@ -648,11 +690,12 @@ void Engine<real, DIM>::tstop(int k) {
 template <typename real, int DIM>
 Status Engine<real, DIM>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
-        // lazily fold the overflow store back into the tiles; the pinned
-        // mirror may lag the GPU by a few steps, which only delays this
-        if ((nstep_ & 63) == 0 && h_ctr_[CTR_STASH] > 0) {
-            Status S = repack();
-            if (S.code) return S;
+        if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
+            HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
+                Status S = repack();
+                if (S.code) return S;
+            }
         }
         const int slot = (int)(nstep_ & 1);
         // this step deposits into the zeroed buffer; the field update zeroes
@@ -666,7 +709,7 @@ Status Engine<real, DIM>::step(int nsteps) {
             HIP_OR_FAIL((launch_push_tiles<real, real, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
         tstop(0);
         tstart(1);
-        HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, 64, stream_)));
+        HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, kStashBlocks, stream_)));
         tstop(1);
         tstart(2);
         HIP_OR_FAIL((launch_insert<real, DIM>(g_, p_, seg_, lv_, st_, ctr_, slot, moved_, 1024, stream_)));
@@ -694,9 +737,13 @@ Status Engine<real, DIM>::repack() {
     HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
     h_ctr_[CTR_STASH] = nst;
     if (nst == 0) return Status{};
-    std::vector<int32_t> cnt(nseg_), old_start(nseg_);
+    const long long capmax = max_segment_slots([&](int mc) {
+        return use_acc64_ ? tile_lds_bytes<real, double>(g_, mc) : tile_lds_bytes<real, real>(g_, mc);
+    });
+    std::vector<int32_t> cnt(nseg_), old_start(nseg_), old_cap(nseg_);
     HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_OR_FAIL(hipMemcpy(old_start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(old_cap.data(), seg_.cap, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<int32_t> scell(nst), ssp(nst);
     HIP_OR_FAIL(hipMemcpy(scell.data(), st_.cell, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_OR_FAIL(hipMemcpy(ssp.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -710,7 +757,7 @@ Status Engine<real, DIM>::repack() {
     std::vector<int32_t> nstart(nseg_), ncap(nseg_);
     long long total = 0;
     for (int s = 0; s < nseg_; ++s) {
-        const long long cp = seg_capacity(want[s], R_.slack);
+        const long long cp = regrow_capacity(want[s], old_cap[s], R_.slack, capmax);
         nstart[s] = (int32_t)total;
         ncap[s] = (int32_t)cp;
         total += cp;
@@ -1511,9 +1558,12 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
 template <typename real>
 Status BatchEngine<real>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
-        if ((nstep_ & 63) == 0 && h_ctr_[CTR_STASH] > 0) {
-            Status S = repack();
-            if (S.code) return S;
+        if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
+            HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
+                Status S = repack();
+                if (S.code) return S;
+            }
         }
         const int slot = (int)(nstep_ & 1);
         const int jnext = jcur_ ^ 1;
@@ -1529,7 +1579,7 @@ Status BatchEngine<real>::step(int nsteps) {
                                                              lv_, ctr_, slot, f_, deposit_, rn, stream_)));
         timer_stop(timer_, stream_, 0);
         timer_start(timer_, stream_, 1);
-        HIP_OR_FAIL((launch_push_stash_batch<real>(d_runs_, st_, ctr_, f_, deposit_, 64, stream_)));
+        HIP_OR_FAIL((launch_push_stash_batch<real>(d_runs_, st_, ctr_, f_, deposit_, kStashBlocks, stream_)));
         timer_stop(timer_, stream_, 1);
         timer_start(timer_, stream_, 2);
         HIP_OR_FAIL((launch_insert_batch<real>(d_runs_, p_, seg_, lv_, st_, ctr_, slot, moved_, 1024, stream_)));
@@ -1556,8 +1606,15 @@ Status BatchEngine<real>::repack() {
     HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost));
     h_ctr_[CTR_STASH] = nst;
     if (nst == 0) return Status{};
-    std::vector<int32_t> cnt(nseg_);
+    const int saved_chunks = seg_.max_chunks;
+    const long long capmax = max_segment_slots([&](int mc) {
+        seg_.max_chunks = mc;
+        return push_lds();
+    });
+    seg_.max_chunks = saved_chunks;
+    std::vector<int32_t> cnt(nseg_), old_cap(nseg_);
     HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(old_cap.data(), seg_.cap, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<int32_t> scell(nst), stag(nst);
     HIP_OR_FAIL(hipMemcpy(scell.data(), st_.cell, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_OR_FAIL(hipMemcpy(stag.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1573,7 +1630,7 @@ Status BatchEngine<real>::repack() {
     std::vector<int32_t> nstart(nseg_), ncap(nseg_);
     long long total = 0, maxcap = 0;
     for (int s = 0; s < nseg_; ++s) {
-        const long long cp = seg_capacity(want[s], runs_[0].R.slack);
+        const long long cp = regrow_capacity(want[s], old_cap[s], runs_[0].R.slack, capmax);
         nstart[s] = (int32_t)total;
         ncap[s] = (int32_t)cp;
         total += cp;
@@ -1915,6 +1972,7 @@ struct pic_batch {
     bool failed = false;
     std::vector<int32_t> cands;       // tile edges tried by the autotuner
     std::vector<double> tune;         // nrun x ncand: ns of push per particle-step (0: not tried)
+    std::vector<double> kernel_ms;    // ncand + 1: push launch per uniform candidate, then per-run tiles
 };
 
 namespace {
@@ -1949,6 +2007,101 @@ Status batch_build(const std::vector<Resolved>& Rs, const pic_state* inits, cons
     auto* e = new BatchEngine<float>(alloc, stream);
     out.reset(e);
     return e->init(Rs, inits);
+}
+
+constexpr int kTuneSteps = 3;
+
+// One autotuner trial: the batch built from cc, one step untimed, then
+// kTuneSteps steps with the push launch and every run's tiles timed.
+// kernel_ms: the mean push launch; share[r]: run r's tiles' summed time over
+// the number of workgroups of the persistent push (which run side by side),
+// per particle-step, in ns.
+Status tune_trial(int nrun, const pic_config* cc, const pic_state* inits, const pic_allocator* alloc,
+                  hipStream_t stream, double& kernel_ms, std::vector<double>& share) {
+    std::vector<Resolved> Rc;
+    Status S = batch_resolve(nrun, cc, inits, Rc);
+    if (S.code) return S;
+    std::unique_ptr<BatchBase> e;
+    S = batch_build(Rc, inits, alloc, stream, e);
+    if (S.code) return S;
+    std::vector<double> ns(nrun, 0.0);
+    double ms[kTimers];
+    int64_t n[kTimers];
+    int64_t st[7] = {0, 0, 0, 0, 0, 1, 0};
+    if ((S = e->step(1)).code || (S = e->run_time(true, nullptr)).code || (S = e->timing(1)).code ||
+        (S = e->step(kTuneSteps)).code || (S = e->run_time(false, ns.data())).code ||
+        (S = e->timing_read(ms, n, kTimers)).code || (S = e->stats(st, 7)).code)
+        return S;
+    kernel_ms = ms[0] / (double)std::max<int64_t>(n[0], 1);
+    const double width = (double)std::max<int64_t>(st[5], 1);
+    share.assign(nrun, 0.0);
+    for (int r = 0; r < nrun; ++r) {
+        int64_t info[4];
+        e->run_info(r, info);
+        share[r] = ns[r] / width / (kTuneSteps * (double)std::max<int64_t>(info[2], 1));
+    }
+    return Status{};
+}
+
+// Tile autotuner for the runs whose cfg tile is 0 x 0 (tunable).
+//  1. For each candidate edge c, every tunable run takes a c x c tile (a run
+//     whose shared memory cannot hold it keeps the default) and the push
+//     launch is timed: c* is the fastest candidate.
+//  2. Each tunable run takes, among the candidates not larger than c*, the
+//     one with the smallest share of the launch: larger tiles need more
+//     shared memory per workgroup, and the largest tile of the batch sets
+//     how many workgroups fit on a compute unit for all runs.
+//  3. The per-run tiles are timed and kept only if faster than c* for all.
+// cc receives the chosen configs.
+void autotune_tiles(int nrun, const pic_config* cfgs, const pic_state* inits, const std::vector<int>& tunable,
+                    const pic_allocator* alloc, hipStream_t stream, pic_batch* b, std::vector<pic_config>& cc) {
+    const int ncand = (int)(sizeof kTileCandidates / sizeof kTileCandidates[0]);
+    b->cands.assign(kTileCandidates, kTileCandidates + ncand);
+    b->tune.assign((size_t)nrun * ncand, 0.0);
+    b->kernel_ms.assign(ncand + 1, 0.0);
+    std::vector<std::vector<pic_config>> trial(ncand);
+    int cstar = -1;
+    for (int ci = 0; ci < ncand; ++ci) {
+        trial[ci].assign(cfgs, cfgs + nrun);
+        std::vector<char> tried(nrun, 0);
+        for (int r : tunable) {
+            pic_config& c = trial[ci][r];
+            c.tile[0] = c.tile[1] = kTileCandidates[ci];
+            Resolved one;
+            if (resolve_config(&c, &inits[r], one).code) c.tile[0] = c.tile[1] = 0;
+            else tried[r] = 1;
+        }
+        if (std::find(tried.begin(), tried.end(), 1) == tried.end()) continue;   // no run takes it
+        double kms = 0.0;
+        std::vector<double> share;
+        if (tune_trial(nrun, trial[ci].data(), inits, alloc, stream, kms, share).code) continue;
+        b->kernel_ms[ci] = kms;
+        for (int r : tunable)
+            if (tried[r]) b->tune[(size_t)r * ncand + ci] = share[r];
+        if (cstar < 0 || kms < b->kernel_ms[cstar]) cstar = ci;
+    }
+    cc.assign(cfgs, cfgs + nrun);
+    if (cstar < 0) return;   // nothing could be timed: the default tiles
+    cc = trial[cstar];
+    std::vector<pic_config> mixed = trial[cstar];
+    bool differs = false;
+    for (int r : tunable) {
+        int best = -1;
+        for (int ci = 0; ci <= cstar; ++ci) {
+            const double t = b->tune[(size_t)r * ncand + ci];
+            if (t > 0.0 && (best < 0 || t < b->tune[(size_t)r * ncand + best])) best = ci;
+        }
+        if (best >= 0 && best != cstar) {
+            mixed[r].tile[0] = mixed[r].tile[1] = kTileCandidates[best];
+            differs = true;
+        }
+    }
+    if (!differs) return;
+    double kms = 0.0;
+    std::vector<double> share;
+    if (tune_trial(nrun, mixed.data(), inits, alloc, stream, kms, share).code) return;
+    b->kernel_ms[ncand] = kms;
+    if (kms < b->kernel_ms[cstar]) cc = mixed;
 }
 
 int batch_finish(pic_batch* b, const Status& s) {
@@ -1996,58 +2149,12 @@ int pic_batch_init(int32_t nrun, const pic_config* cfgs, const pic_state* inits,
         return S.code;
     }
     auto* b = new pic_batch();
-    const int ncand = (int)(sizeof kTileCandidates / sizeof kTileCandidates[0]);
     std::vector<int> tunable;
     for (int r = 0; r < nrun; ++r)
         if (autotune && cfgs[r].tile[0] == 0 && cfgs[r].tile[1] == 0) tunable.push_back(r);
     if (!tunable.empty()) {
-        // Autotune: build the batch with each candidate tile for the tunable
-        // runs, time two steps of each run's tiles, keep each run's fastest.
-        b->cands.assign(kTileCandidates, kTileCandidates + ncand);
-        b->tune.assign((size_t)nrun * ncand, 0.0);
-        std::vector<double> best(nrun, 1e300);
-        std::vector<int> best_t(nrun, 16);
-        for (int ci = 0; ci < ncand; ++ci) {
-            // a run that cannot take this candidate (shared memory) keeps the
-            // default tile in this trial and records no time for it
-            std::vector<pic_config> cc(cfgs, cfgs + nrun);
-            std::vector<char> tried(nrun, 0);
-            for (int r : tunable) {
-                cc[r].tile[0] = kTileCandidates[ci];
-                cc[r].tile[1] = kTileCandidates[ci];
-                Resolved one;
-                if (resolve_config(&cc[r], &inits[r], one).code) {
-                    cc[r].tile[0] = 0;
-                    cc[r].tile[1] = 0;
-                } else {
-                    tried[r] = 1;
-                }
-            }
-            std::vector<Resolved> Rc;
-            if (batch_resolve(nrun, cc.data(), inits, Rc).code) continue;
-            std::unique_ptr<BatchBase> e;
-            if (batch_build(Rc, inits, alloc, stream, e).code) continue;
-            std::vector<double> ns(nrun, 0.0);
-            if (e->step(1).code || e->run_time(true, nullptr).code || e->step(2).code ||
-                e->run_time(false, ns.data()).code)
-                continue;
-            for (int r : tunable) {
-                if (!tried[r]) continue;
-                int64_t info[4];
-                e->run_info(r, info);
-                const double t = ns[r] / (2.0 * (double)std::max<int64_t>(info[2], 1));
-                b->tune[(size_t)r * ncand + ci] = t;
-                if (t < best[r]) {
-                    best[r] = t;
-                    best_t[r] = kTileCandidates[ci];
-                }
-            }
-        }
-        std::vector<pic_config> cc(cfgs, cfgs + nrun);
-        for (int r : tunable) {
-            cc[r].tile[0] = best_t[r];
-            cc[r].tile[1] = best_t[r];
-        }
+        std::vector<pic_config> cc;
+        autotune_tiles(nrun, cfgs, inits, tunable, alloc, stream, b, cc);
         S = batch_resolve(nrun, cc.data(), inits, Rs);
         if (S.code) {
             g_init_error = S.msg;
@@ -2105,17 +2212,19 @@ int pic_batch_info(pic_batch* b, int32_t run, int64_t out[4]) {
     return PIC_OK;
 }
 
-int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, int32_t cap_cand, int32_t* ncand_out) {
+int pic_batch_tuning(pic_batch* b, int32_t* cand_out, double* ns_out, double* kernel_ms_out, int32_t cap_cand,
+                     int32_t* ncand_out) {
     BATCH_CHECK(b);
     const int nc = (int)b->cands.size();
     if (ncand_out) *ncand_out = nc;
     if (nc == 0) return PIC_OK;
-    if (cap_cand < nc || !cand_out || !ns_out) {
+    if (cap_cand < nc || !cand_out || !ns_out || !kernel_ms_out) {
         b->err = "cap_cand too small or NULL output";
         return PIC_EINVAL;
     }
     for (int i = 0; i < nc; ++i) cand_out[i] = b->cands[i];
     std::copy(b->tune.begin(), b->tune.end(), ns_out);
+    std::copy(b->kernel_ms.begin(), b->kernel_ms.end(), kernel_ms_out);
     return PIC_OK;
 }
 

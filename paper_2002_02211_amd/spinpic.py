@@ -125,7 +125,7 @@ def load_library(path=LIB_PATH):
     lib.pic_batch_fields.argtypes = [P, ctypes.c_int32, ctypes.c_uint32, D, ctypes.c_size_t]
     lib.pic_batch_particles.argtypes = [P, ctypes.c_int32, ctypes.c_int32, D, ctypes.c_size_t, I64]
     lib.pic_batch_info.argtypes = [P, ctypes.c_int32, I64]
-    lib.pic_batch_tuning.argtypes = [P, I32, D, ctypes.c_int32, I32]
+    lib.pic_batch_tuning.argtypes = [P, I32, D, D, ctypes.c_int32, I32]
     lib.pic_batch_stats.argtypes = [P, I64, ctypes.c_int32]
     lib.pic_batch_timing.argtypes = [P, ctypes.c_int32]
     lib.pic_batch_timing_read.argtypes = [P, D, I64, ctypes.c_int32]
@@ -588,14 +588,22 @@ class Batch:
         return {"tile": (out[0], out[1]), "particles": out[2], "cells": out[3]}
 
     def tuning(self):
-        """(candidate tile edges, (nruns, ncand) ns per particle-step) or None."""
+        """None if nothing was tuned, else a dict: candidates (tile edges),
+        share_ns ((nruns, ncand) ns per particle-step of each run's tiles over
+        the push's workgroups, 0 where not tried), kernel_ms (push launch per
+        uniform candidate) and mixed_ms (push launch with per-run tiles, 0 if
+        not tried)."""
         nc = ctypes.c_int32()
         cands = (ctypes.c_int32 * 16)()
         ns = np.zeros(self.nruns * 16)
-        _batch_check(load_library().pic_batch_tuning(self.h, cands, _dptr(ns), 16, ctypes.byref(nc)), self.h)
-        if nc.value == 0:
+        kms = np.zeros(17)
+        _batch_check(load_library().pic_batch_tuning(self.h, cands, _dptr(ns), _dptr(kms), 16, ctypes.byref(nc)),
+                     self.h)
+        n = nc.value
+        if n == 0:
             return None
-        return list(cands[: nc.value]), ns[: self.nruns * nc.value].reshape(self.nruns, nc.value)
+        return {"candidates": list(cands[:n]), "share_ns": ns[: self.nruns * n].reshape(self.nruns, n),
+                "kernel_ms": kms[:n].copy(), "mixed_ms": float(kms[n])}
 
     def stats(self):
         out = (ctypes.c_int64 * 7)()
