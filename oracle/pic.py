@@ -49,9 +49,16 @@ AXIS = (2, 1, 0)
 
 
 class Grid:
-    """Periodic Yee grid: ``ndim`` = 2 (x, y; d/dz = 0) or 3; n and d per axis."""
+    """Yee grid: ``ndim`` = 2 (x, y; d/dz = 0) or 3; n and d per axis.
 
-    def __init__(self, ndim, n, d, dt):
+    Periodic in every axis, or with ``open_x`` open along x: the fields
+    beyond the two x faces read as zero for the gather, current deposited
+    there is lost, particles crossing them leave the box, and the field
+    update takes the ghost values of the outgoing-wave condition (see
+    yee_step)."""
+
+    def __init__(self, ndim, n, d, dt, open_x=False):
+        self.open_x = bool(open_x)
         self.ndim = int(ndim)
         self.n = tuple(int(v) for v in n)
         if self.ndim == 2:
@@ -81,10 +88,14 @@ def interpolate(F, xi, stagger, grid):
     for corner in itertools.product((0, 1), repeat=grid.ndim):
         weight = np.ones(xi.shape[0])
         ind = [np.zeros(xi.shape[0], dtype=np.int64)] * 3
+        inside = np.ones(xi.shape[0], dtype=bool)
         for a in range(grid.ndim):
             weight = weight * (frac[a] if corner[a] else 1.0 - frac[a])
-            ind[a] = (idx[a] + corner[a]) % grid.n[a]
-        val += weight * F[ind[2], ind[1], ind[0]]
+            raw = idx[a] + corner[a]
+            if a == 0 and grid.open_x:
+                inside = (raw >= 0) & (raw < grid.n[0])
+            ind[a] = raw % grid.n[a]
+        val += np.where(inside, weight * F[ind[2], ind[1], ind[0]], 0.0)
     return val
 
 
@@ -167,9 +178,11 @@ def move(xi, u_new, grid):
 
 
 def wrap(xi, grid):
-    """Periodic wrap of positions into [0, n) along every active axis."""
+    """Periodic wrap of positions into [0, n) along every active periodic axis."""
     out = xi.copy()
     for a in range(grid.ndim):
+        if a == 0 and grid.open_x:
+            continue
         p = np.mod(xi[:, a], grid.n[a])
         out[:, a] = np.where(p >= grid.n[a], p - grid.n[a], p)
     return out
@@ -203,7 +216,13 @@ def shape_pair(p0, p1):
 
 
 def _scatter(F, ind, values, grid):
-    """F[ind] += values with periodic indices; ind is a list (ix, iy, iz)."""
+    """F[ind] += values with periodic indices; ind is a list (ix, iy, iz).
+    With an open x axis, values at x indices outside [0, n) are dropped."""
+    values = np.broadcast_to(values, np.shape(ind[0]))
+    if grid.open_x:
+        keep = (ind[0] >= 0) & (ind[0] < grid.n[0])
+        ind = [np.broadcast_to(i, keep.shape)[keep] for i in ind]
+        values = values[keep]
     flat = ((ind[2] % grid.n[2]) * grid.n[1] + (ind[1] % grid.n[1])) * grid.n[0] \
         + (ind[0] % grid.n[0])
     F += np.bincount(flat.ravel(), weights=values.ravel(),
@@ -285,45 +304,76 @@ def charge_density(xi, Zw, grid):
 
 # ---------------------------------------------------------------- Yee
 
-def _dplus(F, a, grid):
-    """Forward difference along axis a: (F[i+1] - F[i]) / d_a (0 along z in 2D)."""
+def _dplus(F, a, grid, ghost=None):
+    """Forward difference along axis a: (F[i+1] - F[i]) / d_a (0 along z in 2D).
+    Along an open x axis F[n] is the ghost column (zero if None)."""
+    if a == 0 and grid.open_x:
+        g = np.zeros_like(F[..., :1]) if ghost is None else ghost
+        return (np.concatenate([F[..., 1:], g], axis=-1) - F) / grid.d[0]
     return (np.roll(F, -1, axis=AXIS[a]) - F) / grid.d[a]
 
 
-def _dminus(F, a, grid):
-    """Backward difference along axis a: (F[i] - F[i-1]) / d_a."""
+def _dminus(F, a, grid, ghost=None):
+    """Backward difference along axis a: (F[i] - F[i-1]) / d_a.  Along an open
+    x axis F[-1] is the ghost column (zero if None)."""
+    if a == 0 and grid.open_x:
+        g = np.zeros_like(F[..., :1]) if ghost is None else ghost
+        return (F - np.concatenate([g, F[..., :-1]], axis=-1)) / grid.d[0]
     return (F - np.roll(F, 1, axis=AXIS[a])) / grid.d[a]
 
 
-def curl_E(E, grid):
-    """curl E at the B positions."""
+# Ghost columns of the open x faces.  A wave leaving through a face carries
+# B = n x E with n the outward normal, so at the high face E_y = B_z and
+# E_z = -B_y, at the low face E_y = -B_z and E_z = B_y.  Each relation is
+# imposed half a cell outside the last E (high face) or B (low face) column,
+# where the ghost and the neighbouring column average to the Yee position of
+# the other field.
+
+def _ghost_E_high(E, B):
+    """E_y and E_z at x index n from the last columns."""
+    return 2.0 * B[2][..., -1:] - E[1][..., -1:], -2.0 * B[1][..., -1:] - E[2][..., -1:]
+
+
+def _ghost_B_low(E, B):
+    """B_y and B_z at x index -1 from the first columns."""
+    return 2.0 * E[2][..., :1] - B[1][..., :1], -2.0 * E[1][..., :1] - B[2][..., :1]
+
+
+def curl_E(E, grid, B=None):
+    """curl E at the B positions (B: for the ghosts of an open x axis)."""
+    gy = gz = None
+    if grid.open_x:
+        gy, gz = _ghost_E_high(E, B)
     return np.stack([
         _dplus(E[2], 1, grid) - _dplus(E[1], 2, grid),
-        _dplus(E[0], 2, grid) - _dplus(E[2], 0, grid),
-        _dplus(E[1], 0, grid) - _dplus(E[0], 1, grid),
+        _dplus(E[0], 2, grid) - _dplus(E[2], 0, grid, gz),
+        _dplus(E[1], 0, grid, gy) - _dplus(E[0], 1, grid),
     ])
 
 
-def curl_B(B, grid):
-    """curl B at the E positions."""
+def curl_B(B, grid, E=None):
+    """curl B at the E positions (E: for the ghosts of an open x axis)."""
+    gy = gz = None
+    if grid.open_x:
+        gy, gz = _ghost_B_low(E, B)
     return np.stack([
         _dminus(B[2], 1, grid) - _dminus(B[1], 2, grid),
-        _dminus(B[0], 2, grid) - _dminus(B[2], 0, grid),
-        _dminus(B[1], 0, grid) - _dminus(B[0], 1, grid),
+        _dminus(B[0], 2, grid) - _dminus(B[2], 0, grid, gz),
+        _dminus(B[1], 0, grid, gy) - _dminus(B[0], 1, grid),
     ])
 
 
 def div_E(E, grid):
-    """Discrete divergence of E at the nodes."""
+    """Discrete divergence of E at the nodes (E beyond an open x face is 0)."""
     return _dminus(E[0], 0, grid) + _dminus(E[1], 1, grid) + _dminus(E[2], 2, grid)
 
 
 def yee_step(E, B, J, grid):
     """B -= dt/2 curl E; E += dt (curl B - J); B -= dt/2 curl E (in place)."""
     dt = grid.dt
-    B -= 0.5 * dt * curl_E(E, grid)
-    E += dt * (curl_B(B, grid) - J)
-    B -= 0.5 * dt * curl_E(E, grid)
+    B -= 0.5 * dt * curl_E(E, grid, B)
+    E += dt * (curl_B(B, grid, E) - J)
+    B -= 0.5 * dt * curl_E(E, grid, B)
 
 
 # ---------------------------------------------------------------- Eq. 4
@@ -398,8 +448,11 @@ class Sim:
 
     CHUNK = 1 << 20
 
-    def __init__(self, spec, state, test_particle=False, store_fp32=False):
-        self.grid = Grid(spec["ndim"], spec["n"], spec["d"], spec["dt"])
+    def __init__(self, spec, state, test_particle=False, store_fp32=False, window=None):
+        # window: a co-moving window (see _advance_window) with open x faces;
+        # a dict with speed, shift_cells, ppc, n0, ramp_start, ramp_len, s0
+        self.window = dict(window) if window is not None else None
+        self.grid = Grid(spec["ndim"], spec["n"], spec["d"], spec["dt"], open_x=window is not None)
         g = self.grid
         self.test_particle = bool(test_particle)
         # store_fp32: after every step, round each particle's in-cell offsets,
@@ -423,6 +476,11 @@ class Sim:
             for k in range(len(self.xi)):
                 self._round_fp32(k, 0, self.xi[k].shape[0])
                 self.w[k] = self.w[k].astype(np.float32).astype(np.float64)
+        # particle ids: the row index of the initial state, then the ids of
+        # injected particles (see _inject)
+        self.ids = [np.arange(x.shape[0], dtype=np.int64) for x in self.xi]
+        self.next_id = [x.shape[0] for x in self.xi]
+        self.shifts = 0
         F = np.asarray(state["fields"], dtype=np.float64).reshape((6,) + g.shape)
         self.E = F[0:3].copy()
         self.B = F[3:6].copy()
@@ -448,7 +506,9 @@ class Sim:
             up = off >= 1.0                 # rounded up to the next cell edge
             fl = np.where(up, fl + 1.0, fl)
             off = np.where(up, 0.0, off)
-            xi[:, a] = np.mod(fl, self.grid.n[a]) + off
+            if not (a == 0 and self.grid.open_x):
+                fl = np.mod(fl, self.grid.n[a])
+            xi[:, a] = fl + off
         self.u[k][lo:hi] = f32(self.u[k][lo:hi])
         self.s[k][lo:hi] = f32(self.s[k][lo:hi])
 
@@ -479,9 +539,89 @@ class Sim:
                 for lo in range(0, n, self.CHUNK):
                     self.push_species(k, lo, min(n, lo + self.CHUNK),
                                       deposit_current=not self.test_particle)
+                if self.grid.open_x:
+                    # particles that crossed an x face leave the box
+                    x = self.xi[k][:, 0]
+                    self._keep(k, (x >= 0.0) & (x < self.grid.n[0]))
             if not self.test_particle:
                 yee_step(self.E, self.B, self.J, self.grid)
             self.nstep += 1
+            if self.window is not None:
+                self._advance_window()
+
+    def _keep(self, k, mask):
+        for arrs in (self.xi, self.u, self.s, self.w, self.ids):
+            arrs[k] = arrs[k][mask]
+
+    # ------------------------------------------------------------ moving window
+
+    def window_density(self, x):
+        """Density of the plasma ahead of the window at lab-frame x: n0 times
+        a linear ramp from ramp_start over ramp_len (a step if ramp_len is 0)."""
+        w = self.window
+        if w["ramp_len"] > 0.0:
+            return w["n0"] * np.clip((x - w["ramp_start"]) / w["ramp_len"], 0.0, 1.0)
+        return np.where(x >= w["ramp_start"], w["n0"], 0.0)
+
+    def _advance_window(self):
+        """After step n the window has moved n speed dt; every whole
+        shift_cells cells of that it shifts the box by shift_cells cells."""
+        w, g = self.window, self.grid
+        S = int(w["shift_cells"])
+        while self.nstep * w["speed"] * g.dt >= (self.shifts + 1) * S * g.d[0]:
+            self._shift(S)
+
+    def _shift(self, S):
+        """Move the box S cells along +x: fields, currents and particles move
+        S cells towards -x in box coordinates, the first S columns leave, the
+        last S columns start with zero fields and fresh plasma."""
+        g = self.grid
+        nx = g.n[0]
+        for F in (self.E, self.B, self.J):
+            F[..., :nx - S] = F[..., S:].copy()
+            F[..., nx - S:] = 0.0
+        self.shifts += 1
+        for k in range(len(self.species)):
+            self.xi[k][:, 0] -= S
+            self._keep(k, self.xi[k][:, 0] >= 0.0)
+        self._inject(S)
+
+    def _inject(self, S):
+        """Cold plasma in the new columns nx-S .. nx-1: in every cell whose
+        centre sees density n > 0 (lab frame), ppc particles of every species
+        at in-cell offset (q + 1/2)/ppc along every axis, u = 0, spin s0,
+        weight n/ppc.  Particle (column col, cell row y, z, q) of a species
+        gets id next_id + ((z ny + y) S + col) ppc + q; next_id then advances
+        by nz ny S ppc whether or not every cell received particles."""
+        w, g = self.window, self.grid
+        ppc = int(w["ppc"])
+        if ppc <= 0:
+            return
+        nx, ny = g.n[0], g.n[1]
+        nz = g.n[2] if g.ndim == 3 else 1
+        origin = self.shifts * S
+        cz, cy, col, q = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(S), np.arange(ppc),
+                                     indexing="ij")
+        cz, cy, col, q = cz.ravel(), cy.ravel(), col.ravel(), q.ravel()
+        cx = nx - S + col
+        dens = self.window_density((cx + 0.5 + origin) * g.d[0])
+        on = dens > 0.0
+        f = (q + 0.5) / ppc
+        xi = np.zeros((cx.size, 3))
+        xi[:, 0] = cx + f
+        xi[:, 1] = cy + f
+        if g.ndim == 3:
+            xi[:, 2] = cz + f
+        s0 = np.asarray(w["s0"], dtype=np.float64)
+        for k in range(len(self.species)):
+            ids = self.next_id[k] + ((cz * ny + cy) * S + col) * ppc + q
+            m = int(on.sum())
+            self.xi[k] = np.concatenate([self.xi[k], xi[on]])
+            self.u[k] = np.concatenate([self.u[k], np.zeros((m, 3))])
+            self.s[k] = np.concatenate([self.s[k], np.tile(s0, (m, 1))])
+            self.w[k] = np.concatenate([self.w[k], dens[on] / ppc])
+            self.ids[k] = np.concatenate([self.ids[k], ids[on]])
+            self.next_id[k] += nz * ny * S * ppc
 
     def select(self, species, emin, emax):
         """Per species, the mask of particles with emin <= E_kin [MeV] < emax."""
@@ -527,17 +667,18 @@ class Sim:
         return np.concatenate([self.E, self.B, self.J, self.rho()[None]], axis=0)
 
     def particles(self, k):
-        """(N, 11): id x y z ux uy uz sx sy sz w, sorted by id."""
+        """(N, 11): id x y z ux uy uz sx sy sz w, sorted by id (positions in
+        box coordinates)."""
         g = self.grid
         n = self.xi[k].shape[0]
         out = np.zeros((n, 11))
-        out[:, 0] = np.arange(n)
+        out[:, 0] = self.ids[k]
         for a in range(g.ndim):
             out[:, 1 + a] = self.xi[k][:, a] * g.d[a]
         out[:, 4:7] = self.u[k]
         out[:, 7:10] = self.s[k]
         out[:, 10] = self.w[k]
-        return out
+        return out[np.argsort(self.ids[k], kind="stable")]
 
     def energy(self):
         """[kinetic energy per species ..., field energy, max|delta(div E - rho)|].

@@ -18,6 +18,7 @@ from oracle import pic as O
 import test_oracle_diag as TD
 import test_oracle_grid as TG
 import test_oracle_push as TP
+import test_oracle_window as TW
 
 
 def _run_all(checks):
@@ -63,6 +64,20 @@ DIAG = [
     TD.test_energy_field_sum_and_kinetic_by_hand,
 ]
 
+WINDOW = [
+    lambda: TW.test_open_faces_absorb_leaving_pulses(1, "y"),
+    lambda: TW.test_open_faces_absorb_leaving_pulses(-1, "y"),
+    lambda: TW.test_open_faces_absorb_leaving_pulses(1, "z"),
+    lambda: TW.test_open_faces_absorb_leaving_pulses(-1, "z"),
+    TW.test_window_follows_a_vacuum_pulse,
+    TW.test_cold_plasma_in_a_moving_window_stays_uniform,
+    TW.test_injected_weights_follow_the_ramp,
+    TW.test_particle_leaving_the_box_is_removed_with_interior_continuity,
+    TW.test_shift_moves_fields_and_clears_new_columns,
+    TW.test_gather_sees_nothing_beyond_the_faces,
+    TW.test_no_current_crosses_a_face,
+]
+
 MUTANTS = [
     ("tbmt_omega", "Omega_v * beta_dot_B * beta", "0.0 * beta_dot_B * beta", PUSH),
     ("tbmt_omega", "- Omega_E * np.cross(beta, Ep)", "+ Omega_E * np.cross(beta, Ep)", PUSH),
@@ -90,30 +105,47 @@ MUTANTS = [
     ("shape_pair", "k0 = (i0 - b)", "k0 = (i1 - b)", GRID),
     ("shape_pair", "S1[rows, k1] = 1.0 - (p1 - i1)", "S1[rows, k1] = 1.0 - (p0 - i0)", GRID),
     ("charge_density", "(frac[a] if corner[a] else 1.0 - frac[a])", "(1.0 - frac[a] if corner[a] else frac[a])", GRID),
-    ("yee_step", "E += dt * (curl_B(B, grid) - J)", "E += dt * (curl_B(B, grid) + J)", GRID),
-    ("yee_step", "B -= 0.5 * dt * curl_E(E, grid)\n    E +=", "B += 0.5 * dt * curl_E(E, grid)\n    E +=", GRID),
-    ("curl_E", "_dplus(E[1], 0, grid) - _dplus(E[0], 1, grid)", "_dplus(E[0], 1, grid) - _dplus(E[1], 0, grid)", GRID),
-    ("curl_B", "_dminus(B[0], 2, grid) - _dminus(B[2], 0, grid)", "_dminus(B[0], 2, grid) + _dminus(B[2], 0, grid)", GRID),
+    ("yee_step", "E += dt * (curl_B(B, grid, E) - J)", "E += dt * (curl_B(B, grid, E) + J)", GRID),
+    ("yee_step", "B -= 0.5 * dt * curl_E(E, grid, B)\n    E +=", "B += 0.5 * dt * curl_E(E, grid, B)\n    E +=", GRID),
+    ("curl_E", "_dplus(E[1], 0, grid, gy) - _dplus(E[0], 1, grid)", "_dplus(E[0], 1, grid) - _dplus(E[1], 0, grid, gy)", GRID),
+    ("curl_B", "_dminus(B[0], 2, grid) - _dminus(B[2], 0, grid, gz)", "_dminus(B[0], 2, grid) + _dminus(B[2], 0, grid, gz)", GRID),
     ("_dplus", "np.roll(F, -1, axis=AXIS[a])", "np.roll(F, 1, axis=AXIS[a])", GRID),
     ("div_E", "_dminus(E[1], 1, grid)", "_dminus(E[1], 0, grid)", GRID),
     ("move", "/ (gamma * grid.d[a])", "/ grid.d[a]", DIAG),
     ("wrap", "np.mod(xi[:, a], grid.n[a])", "np.mod(xi[:, a], grid.n[a] - 1)", DIAG),
     ("polarization", "s[selected].sum(axis=0) / N", "s[selected].sum(axis=0) / max(N - 1, 1)", DIAG),
     ("kinetic_energy_mev", "mu * (gamma - 1.0)", "(gamma - 1.0)", DIAG),
+    ("_ghost_E_high", "2.0 * B[2][..., -1:] - E[1][..., -1:]", "2.0 * B[2][..., -1:] + E[1][..., -1:]", WINDOW),
+    ("_ghost_E_high", "-2.0 * B[1][..., -1:] - E[2][..., -1:]", "2.0 * B[1][..., -1:] - E[2][..., -1:]", WINDOW),
+    ("_ghost_B_low", "-2.0 * E[1][..., :1] - B[2][..., :1]", "2.0 * E[1][..., :1] - B[2][..., :1]", WINDOW),
+    ("_ghost_B_low", "2.0 * E[2][..., :1] - B[1][..., :1]", "2.0 * E[2][..., :1] + B[1][..., :1]", WINDOW),
+    ("_scatter", "(ind[0] < grid.n[0])", "(ind[0] <= grid.n[0])", WINDOW),
+    ("interpolate", "inside = (raw >= 0)", "inside = (raw >= -1)", WINDOW),
+    ("Sim.step", "(x >= 0.0) & (x < self.grid.n[0])", "(x >= -1.0) & (x < self.grid.n[0])", WINDOW),
+    ("Sim._shift", "F[..., :nx - S] = F[..., S:].copy()", "F[..., S:] = F[..., :nx - S].copy()", WINDOW),
+    ("Sim._shift", "F[..., nx - S:] = 0.0", "pass", WINDOW),
+    ("Sim._shift", "self.xi[k][:, 0] -= S", "self.xi[k][:, 0] -= S - 1", WINDOW),
+    ("Sim._inject", "f = (q + 0.5) / ppc", "f = q / ppc", WINDOW),
+    ("Sim._inject", "((cz * ny + cy) * S + col) * ppc + q", "((cz * ny + cy) * S + col) + q", WINDOW),
+    ("Sim._inject", "(cx + 0.5 + origin) * g.d[0]", "(cx + origin) * g.d[0]", WINDOW),
+    ("Sim._inject", "self.next_id[k] += nz * ny * S * ppc", "self.next_id[k] += m", WINDOW),
+    ("Sim.window_density", '(x - w["ramp_start"]) / w["ramp_len"]', '(x - w["ramp_start"]) * w["ramp_len"]', WINDOW),
+    ("Sim._advance_window", ">= (self.shifts + 1) * S", ">= (self.shifts + 2) * S", WINDOW),
 ]
 
 
 @pytest.mark.parametrize("fname,old,new,checks", MUTANTS,
                          ids=["%s:%d" % (m[0], i) for i, m in enumerate(MUTANTS)])
 def test_mutant_is_killed(monkeypatch, fname, old, new, checks):
-    src = textwrap.dedent(inspect.getsource(getattr(O, fname)))
+    owner, name = (O.Sim, fname.split(".")[1]) if fname.startswith("Sim.") else (O, fname)
+    src = textwrap.dedent(inspect.getsource(getattr(owner, name)))
     assert old in src, "mutation snippet not found in %s" % fname
     glb = dict(O.__dict__)
     exec(compile(src.replace(old, new, 1), "<mutant %s>" % fname, "exec"), glb)
-    monkeypatch.setattr(O, fname, glb[fname])
+    monkeypatch.setattr(owner, name, glb[name])
     assert _run_all(checks), "mutant of %s survived: %r -> %r" % (fname, old, new)
 
 
 def test_unmutated_oracle_passes_every_check():
-    for chk in PUSH + GRID + DIAG:
+    for chk in PUSH + GRID + DIAG + WINDOW:
         chk()

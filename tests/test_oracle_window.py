@@ -1,0 +1,268 @@
+"""Pins of the oracle's co-moving window and open x faces (the co-moving
+frame of the paper's runs, section 2; the boundary conditions are readings
+of the paper, listed with the design notes).
+
+* Open faces absorb: a pulse leaving through either x face, in either
+  polarization, leaves behind less than 1 % of its energy; with the ghost
+  columns replaced by zero (a conducting wall) nearly all of it stays.
+* A window moving at c with a vacuum pulse equals the same pulse in a
+  periodic box twice as long, read at the window's offset.
+* A cold uniform plasma in a moving window stays uniform, neutral and on
+  its lattice, the particle count per species is constant, and ids of
+  injected particles follow the stated rule.
+* Injected weights follow the density ramp in the lab frame.
+* A particle crossing a face is removed; charge continuity holds on the
+  interior nodes of that step.
+* Away from the faces an open box is identical to the periodic one until
+  signals from the faces can arrive.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.pic import Grid, Sim
+
+D = 0.05 * 2 * np.pi
+EMPTY = [np.zeros((0, 10))]
+
+
+def _vac_spec(nx, ny, nsp=1):
+    dt = 0.95 / np.sqrt(2 / D ** 2)
+    sp = [{"Z": -1.0, "mu": 1.0, "a": 0.00116}, {"Z": 1.0, "mu": 1836.15267343, "a": 1.793}][:nsp]
+    return {"ndim": 2, "n": (nx, ny, 1), "d": (D, D, 1.0), "dt": dt, "species": sp}
+
+
+def _pulse(nx, ny, xc, L, direction=1, pol="y"):
+    """A vacuum pulse moving along +-x: E at its Yee position, B = n x E at
+    its own (half a cell further along x)."""
+    x = np.arange(nx) * D
+    f = lambda x: np.exp(-((x - xc) / L) ** 2) * np.cos(x)
+    F = np.zeros((6, 1, ny, nx))
+    if pol == "y":
+        F[1, 0] = f(x)[None, :]
+        F[5, 0] = direction * f(x + 0.5 * D)[None, :]
+    else:
+        F[2, 0] = f(x)[None, :]
+        F[4, 0] = -direction * f(x + 0.5 * D)[None, :]
+    return F
+
+
+def _window(speed=1.0, S=4, ppc=0, n0=0.0, ramp_start=0.0, ramp_len=0.0, s0=(0.0, 1.0, 0.0)):
+    return dict(speed=speed, shift_cells=S, ppc=ppc, n0=n0, ramp_start=ramp_start, ramp_len=ramp_len, s0=s0)
+
+
+def _energy(sim):
+    return float(np.sum(sim.E ** 2) + np.sum(sim.B ** 2))
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("pol", ["y", "z"])
+def test_open_faces_absorb_leaving_pulses(direction, pol):
+    nx, ny = 400, 4
+    spec = _vac_spec(nx, ny)
+    F = _pulse(nx, ny, 0.5 * nx * D, 3 * 2 * np.pi, direction, pol)
+    sim = Sim(spec, {"particles": EMPTY, "fields": F}, window=_window(speed=0.0))
+    w0 = _energy(sim)
+    sim.step(int(1.2 * nx * D / sim.grid.dt))
+    assert sim.shifts == 0
+    assert _energy(sim) / w0 < 1e-2
+
+
+def test_zero_ghosts_reflect_instead():
+    """Negative control: a conducting wall (ghost columns zero) keeps the pulse."""
+    nx, ny = 400, 4
+    spec = _vac_spec(nx, ny)
+    F = _pulse(nx, ny, 0.5 * nx * D, 3 * 2 * np.pi)
+    sim = Sim(spec, {"particles": EMPTY, "fields": F}, window=_window(speed=0.0))
+    g = sim.grid
+    w0 = _energy(sim)
+    for _ in range(int(1.2 * nx * D / g.dt)):
+        dt = g.dt
+        sim.B -= 0.5 * dt * np.stack([oracle.pic._dplus(sim.E[2], 1, g),
+                                      -oracle.pic._dplus(sim.E[2], 0, g),
+                                      oracle.pic._dplus(sim.E[1], 0, g) - oracle.pic._dplus(sim.E[0], 1, g)])
+        sim.E += dt * np.stack([oracle.pic._dminus(sim.B[2], 1, g),
+                                -oracle.pic._dminus(sim.B[2], 0, g),
+                                oracle.pic._dminus(sim.B[1], 0, g) - oracle.pic._dminus(sim.B[0], 1, g)])
+        sim.B -= 0.5 * dt * np.stack([oracle.pic._dplus(sim.E[2], 1, g),
+                                      -oracle.pic._dplus(sim.E[2], 0, g),
+                                      oracle.pic._dplus(sim.E[1], 0, g) - oracle.pic._dplus(sim.E[0], 1, g)])
+    assert _energy(sim) / w0 > 0.5
+
+
+def test_window_follows_a_vacuum_pulse():
+    nx, ny, S, N = 400, 4, 4, 150
+    F = _pulse(nx, ny, 0.5 * nx * D, 1.5 * 2 * np.pi)
+    a = Sim(_vac_spec(nx, ny), {"particles": EMPTY, "fields": F}, window=_window(S=S))
+    F2 = np.zeros((6, 1, ny, 2 * nx))
+    F2[..., :nx] = F
+    b = Sim(_vac_spec(2 * nx, ny), {"particles": EMPTY, "fields": F2})
+    a.step(N)
+    b.step(N)
+    # N dt of travel at c is N * 0.6718 cells: 100.8 cells, 25 whole shifts of 4
+    assert a.shifts == int(N * a.grid.dt / (S * D))
+    off = a.shifts * S
+    scale = np.max(np.abs(b.E))
+    assert np.max(np.abs(a.E - b.E[..., off:off + nx])) < 1e-3 * scale
+    assert np.max(np.abs(a.B - b.B[..., off:off + nx])) < 1e-3 * scale
+    # read one cell off, the two differ at the level of the pulse itself
+    assert np.max(np.abs(a.E - b.E[..., off + 1:off + 1 + nx])) > 0.1 * scale
+
+
+def _lattice_state(spec, ppc, n0):
+    """A cold neutral plasma on the injection lattice of every cell."""
+    nx, ny = spec["n"][0], spec["n"][1]
+    cy, cx, q = np.meshgrid(np.arange(ny), np.arange(nx), np.arange(ppc), indexing="ij")
+    f = (q.ravel() + 0.5) / ppc
+    rows = np.zeros((cx.size, 10))
+    rows[:, 0] = (cx.ravel() + f) * spec["d"][0]
+    rows[:, 1] = (cy.ravel() + f) * spec["d"][1]
+    rows[:, 7] = 1.0
+    rows[:, 9] = n0 / ppc
+    return {"particles": [rows.copy(), rows.copy()], "fields": np.zeros((6, 1, ny, nx))}
+
+
+def test_cold_plasma_in_a_moving_window_stays_uniform():
+    nx, ny, S, ppc, n0 = 48, 6, 4, 3, 0.01
+    spec = _vac_spec(nx, ny, nsp=2)
+    st = _lattice_state(spec, ppc, n0)
+    sim = Sim(spec, st, window=_window(S=S, ppc=ppc, n0=n0))
+    n_start = [x.shape[0] for x in sim.xi]
+    sim.step(60)
+    assert sim.shifts == int(60 * sim.grid.dt / (S * D)) > 5
+    for k in range(2):
+        assert sim.xi[k].shape[0] == n_start[k]
+        ids = sim.ids[k]
+        assert np.unique(ids).size == ids.size
+        # every particle sits on the lattice of its cell
+        f = sim.xi[k][:, :2] - np.floor(sim.xi[k][:, :2])
+        lat = (np.arange(ppc) + 0.5) / ppc
+        assert np.all(np.min(np.abs(f[:, :1] - lat[None, :]), axis=1) < 1e-12)
+        assert np.allclose(f[:, 0], f[:, 1], atol=1e-12)
+        assert np.all(sim.u[k] == 0.0) and np.allclose(sim.w[k], n0 / ppc)
+        # ids: the original particles of columns >= shifts * S, then the
+        # injected ones, next_id advancing by ny S ppc per shift
+        assert sim.next_id[k] == n_start[k] + sim.shifts * ny * S * ppc
+        assert ids.max() < sim.next_id[k]
+        newest = ids >= sim.next_id[k] - ny * S * ppc
+        assert newest.sum() == ny * S * ppc
+        assert np.all(sim.xi[k][newest, 0] >= nx - S)
+    assert np.max(np.abs(sim.rho())) == 0.0
+    assert np.max(np.abs(sim.E)) == 0.0 and np.max(np.abs(sim.B)) == 0.0
+
+
+def test_injected_weights_follow_the_ramp():
+    nx, ny, S, ppc, n0 = 40, 3, 4, 2, 0.02
+    start, length = nx * D + 15.0, 12.0
+    spec = _vac_spec(nx, ny, nsp=1)
+    sim = Sim(spec, {"particles": EMPTY, "fields": np.zeros((6, 1, ny, nx))},
+              window=_window(S=S, ppc=ppc, n0=n0, ramp_start=start, ramp_len=length))
+    sim.step(100)
+    assert sim.shifts > 10
+    x_lab = (np.floor(sim.xi[0][:, 0]) + 0.5 + sim.shifts * S) * D
+    want = n0 * np.minimum(1.0, np.maximum(0.0, (x_lab - start) / length))
+    assert np.allclose(sim.w[0] * ppc, want, rtol=1e-14, atol=0.0)
+    # a column holds ny ppc particles if it entered the box after the start
+    # and its centre lies past the ramp's start, none otherwise
+    cols = np.arange(nx)
+    entered = cols + sim.shifts * S >= nx
+    centre = (cols + 0.5 + sim.shifts * S) * D
+    expect = np.where(entered & (centre > start), ny * ppc, 0)
+    per_col = np.bincount(np.floor(sim.xi[0][:, 0]).astype(int), minlength=nx)
+    assert np.array_equal(per_col, expect) and expect.sum() > 0 and (expect == 0).sum() > 0
+    # ids advance by the full ny S ppc per shift, skipped cells included
+    assert sim.next_id[0] == sim.shifts * ny * S * ppc
+    ids = sim.ids[0]
+    assert np.unique(ids).size == ids.size and ids.max() < sim.next_id[0]
+
+
+def test_particle_leaving_the_box_is_removed_with_interior_continuity():
+    nx, ny = 12, 8
+    spec = _vac_spec(nx, ny, nsp=1)
+    rows = np.array([[0.3 * D, 3.6 * D, 0.0, -5.0, 1.0, 0.5, 0.0, 1.0, 0.0, 1.0],
+                     [5.2 * D, 4.1 * D, 0.0, 2.0, -3.0, 0.1, 0.0, 1.0, 0.0, 1.0]])
+    sim = Sim(spec, {"particles": [rows], "fields": np.zeros((6, 1, ny, nx))}, window=_window(speed=0.0))
+    g = sim.grid
+    rho0 = sim.rho()
+    xi0 = sim.xi[0].copy()
+    sim.J[...] = 0.0
+    sim.push_species(0, 0, 2)
+    xi1 = sim.xi[0].copy()
+    assert xi1[0, 0] < 0.0 <= xi1[1, 0]
+    # charge after the move, particle 0 included where it lands (its charge
+    # on the x = 0 node is partly still inside)
+    rho1 = oracle.charge_density(xi1, -1.0 * sim.w[0], g)
+    divJ = (sim.J[0] - np.roll(sim.J[0], 1, axis=2)) / g.d[0] + (sim.J[1] - np.roll(sim.J[1], 1, axis=1)) / g.d[1]
+    cont = (rho1 - rho0) / g.dt + divJ
+    assert np.max(np.abs(cont[..., 2:])) < 1e-12 * np.max(np.abs(sim.J))
+    sim2 = Sim(spec, {"particles": [rows], "fields": np.zeros((6, 1, ny, nx))}, window=_window(speed=0.0))
+    sim2.step(1)
+    assert sim2.xi[0].shape[0] == 1 and sim2.ids[0].tolist() == [1]
+    assert np.allclose(sim2.particles(0)[0, 1:4], xi1[1] * np.array(g.d))
+
+
+def test_open_box_interior_equals_periodic_until_reached():
+    spec = synth.preset("small2d")
+    st = synth.make_state(spec)
+    a = Sim(spec, st)
+    b = Sim(spec, st, window=_window(speed=0.0))
+    N = 6
+    a.step(N)
+    b.step(N)
+    nx = spec["n"][0]
+    # per step fields reach two cells and particles one plus the stencil
+    m = 5 * N
+    inner = slice(m, nx - m)
+    assert nx - 2 * m >= 10
+    assert np.array_equal(a.E[..., inner], b.E[..., inner])
+    assert np.array_equal(a.B[..., inner], b.B[..., inner])
+    assert not np.array_equal(a.E, b.E)
+
+
+def test_shift_moves_fields_and_clears_new_columns():
+    nx, ny, S = 20, 3, 4
+    spec = _vac_spec(nx, ny, nsp=1)
+    rng = np.random.default_rng(1)
+    F = rng.normal(size=(6, 1, ny, nx))
+    sim = Sim(spec, {"particles": EMPTY, "fields": F}, window=_window(S=S))
+    sim.J[...] = rng.normal(size=sim.J.shape)
+    J0 = sim.J.copy()
+    sim._shift(S)
+    assert np.array_equal(sim.E[..., :nx - S], F[0:3][..., S:])
+    assert np.array_equal(sim.B[..., :nx - S], F[3:6][..., S:])
+    assert np.array_equal(sim.J[..., :nx - S], J0[..., S:])
+    assert not sim.E[..., nx - S:].any() and not sim.B[..., nx - S:].any() and not sim.J[..., nx - S:].any()
+    assert sim.shifts == 1
+
+
+def test_gather_sees_nothing_beyond_the_faces():
+    nx, ny = 10, 4
+    g = Grid(2, (nx, ny, 1), (D, D, 1.0), 0.1, open_x=True)
+    E = np.zeros((3, 1, ny, nx))
+    B = np.zeros((3, 1, ny, nx))
+    E[:, :, :, -1] = 1.0      # only the last column is set
+    B[:, :, :, -1] = 1.0
+    xi = np.array([[0.2, 1.5, 0.0], [0.7, 2.2, 0.0]])   # in the first cell
+    Ep, Bp = oracle.gather(E, B, xi, g)
+    assert not Ep.any() and not Bp.any()
+    E[:, :, :, -1] = 0.0
+    B[:, :, :, -1] = 0.0
+    E[:, :, :, 0] = 1.0
+    B[:, :, :, 0] = 1.0
+    xi = np.array([[nx - 0.8, 1.5, 0.0], [nx - 0.3, 2.2, 0.0]])   # in the last cell
+    Ep, Bp = oracle.gather(E, B, xi, g)
+    assert not Ep.any() and not Bp.any()
+
+
+def test_no_current_crosses_a_face():
+    nx, ny = 12, 8
+    spec = _vac_spec(nx, ny, nsp=1)
+    rows = np.array([[(nx - 0.4) * D, 3.6 * D, 0.0, 6.0, 1.0, 0.5, 0.0, 1.0, 0.0, 1.0]])
+    sim = Sim(spec, {"particles": [rows], "fields": np.zeros((6, 1, ny, nx))}, window=_window(speed=0.0))
+    sim.J[...] = 0.0
+    sim.push_species(0, 0, 1)
+    assert sim.xi[0][0, 0] >= nx
+    assert np.any(sim.J[..., nx - 2:])
+    assert not np.any(sim.J[..., :nx - 3])
