@@ -1141,7 +1141,7 @@ public:
         Geom g;
         double d[3];
         long long cell_off = 0;
-        int sid_base = 0, tile_base = 0;
+        int sid_base = 0, tile_base = 0, fdtd_blk_base = 0;
         long long count_sp[kMaxSpecies] = {0, 0, 0, 0};
         long long npart = 0;
     };
@@ -1201,7 +1201,7 @@ private:
     hipStream_t stream_;
     std::vector<void*> live_;
     std::vector<Run> runs_;
-    int nsp_ = 0, nseg_ = 0, ntiles_ = 0, nx_max_ = 1, ny_max_ = 1;
+    int nsp_ = 0, nseg_ = 0, ntiles_ = 0;
     int use_acc64_ = 1, deposit_ = 1;
     long long cap_total_ = 0, npart_ = 0, ncells_ = 0;
     int64_t nstep_ = 0, repacks_ = 0;
@@ -1219,6 +1219,8 @@ private:
     double* acc_ = nullptr;
     RunDesc<real>* d_runs_ = nullptr;
     TileRef* d_order_ = nullptr;
+    int32_t* d_blk_run_ = nullptr;   // field-update block -> run
+    int fdtd_nblk_ = 0;
     std::vector<TileRef> order_;
     Timer timer_;
 };
@@ -1295,6 +1297,7 @@ Status BatchEngine<real>::upload_descs() {
         D.cell_off = R.cell_off;
         D.sid_base = R.sid_base;
         D.tile_base = R.tile_base;
+        D.fdtd_blk_base = R.fdtd_blk_base;
     }
     HIP_OR_FAIL(hipMemcpyAsync(d_runs_, d.data(), d.size() * sizeof(RunDesc<real>), hipMemcpyHostToDevice, stream_));
     return Status{};
@@ -1329,11 +1332,13 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
         R.cell_off = cells;
         R.sid_base = sids;
         R.tile_base = tiles;
+        R.fdtd_blk_base = fdtd_nblk_;
+        if ((long long)fdtd_nblk_ + fdtd_blocks(R.g.n[0], R.g.n[1]) > (1LL << 30))
+            return fail(PIC_EINVAL, "batch too large for one field-update launch");
+        fdtd_nblk_ += fdtd_blocks(R.g.n[0], R.g.n[1]);
         cells += R.g.ncells;
         sids += R.g.ntiles * nsp_;
         tiles += R.g.ntiles;
-        nx_max_ = std::max(nx_max_, R.g.n[0]);
-        ny_max_ = std::max(ny_max_, R.g.n[1]);
         R.npart = 0;
         for (int s = 0; s < nsp_; ++s) {
             R.count_sp[s] = st[r].count[s];
@@ -1440,7 +1445,9 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     acc_ = (double*)dalloc(8 * sizeof(double));
     d_runs_ = (RunDesc<real>*)dalloc(nrun * sizeof(RunDesc<real>));
     d_order_ = (TileRef*)dalloc(ntiles_ * sizeof(TileRef));
-    bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && run_ns_ && acc_ && d_runs_ && d_order_;
+    d_blk_run_ = (int32_t*)dalloc((size_t)fdtd_nblk_ * sizeof(int32_t));
+    bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && run_ns_ && acc_ && d_runs_ && d_order_ &&
+              d_blk_run_;
     for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
     if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
     HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
@@ -1543,6 +1550,17 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     order_.resize(ntiles_);
     for (int i = 0; i < ntiles_; ++i) order_[i] = cost[i].second;
     HIP_OR_FAIL(hipMemcpyAsync(d_order_, order_.data(), ntiles_ * sizeof(TileRef), hipMemcpyHostToDevice, stream_));
+    {
+        std::vector<int32_t> blk_run((size_t)fdtd_nblk_);
+        for (int r = 0; r < nrun; ++r) {
+            const Run& R = runs_[r];
+            std::fill(blk_run.begin() + R.fdtd_blk_base,
+                      blk_run.begin() + R.fdtd_blk_base + fdtd_blocks(R.g.n[0], R.g.n[1]), r);
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(d_blk_run_, blk_run.data(), blk_run.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, stream_));
+        HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    }
     S = upload_descs();
     if (S.code) return S;
     int dev = 0, cus = 256;
@@ -1586,9 +1604,9 @@ Status BatchEngine<real>::step(int nsteps) {
         timer_stop(timer_, stream_, 2);
         if (deposit_) {
             timer_start(timer_, stream_, 3);
-            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, stream_)));
-            HIP_OR_FAIL((launch_fdtd_e_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, jbuf_[jcur_], stream_)));
-            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, nruns(), nx_max_, ny_max_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_e_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, jbuf_[jcur_], stream_)));
+            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, stream_)));
             timer_stop(timer_, stream_, 3);
         }
         HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost, stream_));

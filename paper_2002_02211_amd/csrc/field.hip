@@ -102,23 +102,36 @@ __device__ inline Fields<freal> offset_fields(const Fields<freal>& f, long long 
     return r;
 }
 
+// Block b of the batch's field update: its run, and the cell (i, j) of this
+// thread in that run (false outside the run's grid).
+template <typename real>
+__device__ inline bool batch_cell(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run,
+                                  int& run, int& i, int& j) {
+    static_assert(kFx == 64 && kFy == 4, "fdtd_blocks() assumes 64 x 4 blocks");
+    run = blk_run[blockIdx.x];
+    const int local = (int)blockIdx.x - runs[run].fdtd_blk_base;
+    const int bx = fdtd_blocks_x(runs[run].g.n[0]);
+    i = (local % bx) * kFx + (int)threadIdx.x;
+    j = (local / bx) * kFy + (int)threadIdx.y;
+    return i < runs[run].g.n[0] && j < runs[run].g.n[1];
+}
+
 template <typename real>
 __global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_b_batch(const RunDesc<real>* __restrict__ runs, Fields<freal> f) {
-    const RunDesc<real>& rd = runs[blockIdx.z];
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    if (i >= rd.g.n[0] || j >= rd.g.n[1]) return;
+k_fdtd_b_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, Fields<freal> f) {
+    int run, i, j;
+    if (!batch_cell(runs, blk_run, run, i, j)) return;
+    const RunDesc<real>& rd = runs[run];
     fdtd_b_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), i, j, 0);
 }
 
 template <typename real>
 __global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_e_batch(const RunDesc<real>* __restrict__ runs, Fields<freal> f, JClear jclear) {
-    const RunDesc<real>& rd = runs[blockIdx.z];
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    if (i >= rd.g.n[0] || j >= rd.g.n[1]) return;
+k_fdtd_e_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, Fields<freal> f,
+               JClear jclear) {
+    int run, i, j;
+    if (!batch_cell(runs, blk_run, run, i, j)) return;
+    const RunDesc<real>& rd = runs[run];
     JClear jc = jclear;
     if (jc.c[0])
         for (int a = 0; a < 3; ++a) jc.c[a] = static_cast<freal*>(jc.c[a]) + rd.cell_off;
@@ -417,31 +430,29 @@ hipError_t launch_bin_particles(const Geom& g, const PArrays<real>& p, const Seg
 }
 
 template <typename real>
-hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
                                const Fields<freal>& f, hipStream_t stream) {
-    const dim3 grid((nx_max + kFx - 1) / kFx, (ny_max + kFy - 1) / kFy, nruns);
-    hipLaunchKernelGGL((k_fdtd_b_batch<real>), grid, dim3(kFx, kFy), 0, stream, runs, f);
+    hipLaunchKernelGGL((k_fdtd_b_batch<real>), dim3(nblocks), dim3(kFx, kFy), 0, stream, runs, blk_run, f);
     return hipGetLastError();
 }
 
 template <typename real>
-hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
                                const Fields<freal>& f, freal* const* jclear, hipStream_t stream) {
     JClear jc{{nullptr, nullptr, nullptr}};
     if (jclear)
         for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
-    const dim3 grid((nx_max + kFx - 1) / kFx, (ny_max + kFy - 1) / kFy, nruns);
-    hipLaunchKernelGGL((k_fdtd_e_batch<real>), grid, dim3(kFx, kFy), 0, stream, runs, f, jc);
+    hipLaunchKernelGGL((k_fdtd_e_batch<real>), dim3(nblocks), dim3(kFx, kFy), 0, stream, runs, blk_run, f, jc);
     return hipGetLastError();
 }
 
-template hipError_t launch_fdtd_b_batch<float>(const RunDesc<float>*, int, int, int, const Fields<freal>&,
+template hipError_t launch_fdtd_b_batch<float>(const RunDesc<float>*, const int32_t*, int, const Fields<freal>&,
                                                hipStream_t);
-template hipError_t launch_fdtd_b_batch<double>(const RunDesc<double>*, int, int, int, const Fields<freal>&,
+template hipError_t launch_fdtd_b_batch<double>(const RunDesc<double>*, const int32_t*, int, const Fields<freal>&,
                                                 hipStream_t);
-template hipError_t launch_fdtd_e_batch<float>(const RunDesc<float>*, int, int, int, const Fields<freal>&,
+template hipError_t launch_fdtd_e_batch<float>(const RunDesc<float>*, const int32_t*, int, const Fields<freal>&,
                                                freal* const*, hipStream_t);
-template hipError_t launch_fdtd_e_batch<double>(const RunDesc<double>*, int, int, int, const Fields<freal>&,
+template hipError_t launch_fdtd_e_batch<double>(const RunDesc<double>*, const int32_t*, int, const Fields<freal>&,
                                                 freal* const*, hipStream_t);
 
 template <typename real>

@@ -42,6 +42,7 @@ struct RunDesc {
     long long cell_off;
     int sid_base;
     int tile_base;
+    int fdtd_blk_base;   // first block of this run in the field-update launches
 };
 
 struct TileRef {
@@ -66,12 +67,16 @@ template <typename real>
 hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p, const Segs& seg,
                                const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
                                unsigned long long* moved, int blocks, hipStream_t stream);
-// Field update of every run: grid (ceil(nx_max / 64), ceil(ny_max / 4), nruns).
+// Field update of every run: each run covered by its own 64 x 4-cell
+// blocks, fdtd_blocks(n) of them from runs[r].fdtd_blk_base on; blk_run[b]
+// is the run of block b (nblocks in all).
+constexpr int fdtd_blocks_x(int nx) { return (nx + 63) / 64; }
+constexpr int fdtd_blocks(int nx, int ny) { return fdtd_blocks_x(nx) * ((ny + 3) / 4); }
 template <typename real>
-hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
                                const Fields<freal>& f, hipStream_t stream);
 template <typename real>
-hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, int nruns, int nx_max, int ny_max,
+hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
                                const Fields<freal>& f, freal* const* jclear, hipStream_t stream);
 
 // Yee update: B -= (dt/2) curl E, or E += dt (curl B - J) while zeroing the
