@@ -54,8 +54,8 @@ class Grid:
     Periodic in every axis, or with ``open_x`` open along x: the fields
     beyond the two x faces read as zero for the gather, current deposited
     there is lost, particles crossing them leave the box, and the field
-    update takes the ghost values of the outgoing-wave condition (see
-    yee_step)."""
+    update takes its ghost columns from Mur's absorbing condition (see
+    MurState)."""
 
     def __init__(self, ndim, n, d, dt, open_x=False):
         self.open_x = bool(open_x)
@@ -322,28 +322,51 @@ def _dminus(F, a, grid, ghost=None):
     return (F - np.roll(F, 1, axis=AXIS[a])) / grid.d[a]
 
 
-# Ghost columns of the open x faces.  A wave leaving through a face carries
-# B = n x E with n the outward normal, so at the high face E_y = B_z and
-# E_z = -B_y, at the low face E_y = -B_z and E_z = B_y.  Each relation is
-# imposed half a cell outside the last E (high face) or B (low face) column,
-# where the ghost and the neighbouring column average to the Yee position of
-# the other field.
+class MurState:
+    """First-order Mur absorbing condition at the two open x faces.
 
-def _ghost_E_high(E, B):
-    """E_y and E_z at x index n from the last columns."""
-    return 2.0 * B[2][..., -1:] - E[1][..., -1:], -2.0 * B[1][..., -1:] - E[2][..., -1:]
+    Beyond each face the Yee update needs one ghost column: E_y and E_z at
+    x index n for the B update, B_y and B_z at x index -1 for the E update.
+    Each ghost follows the one-way wave equation of a wave leaving through
+    its face, discretized midway between the ghost and the first column
+    inside and midway between two time levels (Mur 1981):
+        ghost(new) = inside(old) + k (inside(new) - ghost(old)),
+        k = (c dt - dx) / (c dt + dx),
+    with E at integer and B at half-integer times.  The state holds each
+    face's ghost and first inside column at the last time level; reset()
+    starts both from the first inside column (at the start and after every
+    shift of a moving window)."""
+
+    def __init__(self, E, B, grid):
+        self.k = (grid.dt - grid.d[0]) / (grid.dt + grid.d[0])
+        self.reset(E, B)
+
+    def reset(self, E, B):
+        self.hi_ghost = np.stack([E[1][..., -1:], E[2][..., -1:]])
+        self.hi_prev = self.hi_ghost.copy()
+        self.lo_ghost = np.stack([B[1][..., :1], B[2][..., :1]])
+        self.lo_prev = self.lo_ghost.copy()
+
+    def advance_low(self, B):
+        """B_y, B_z ghosts at the new half step from the first B column."""
+        inside = np.stack([B[1][..., :1], B[2][..., :1]])
+        self.lo_ghost = self.lo_prev + self.k * (inside - self.lo_ghost)
+        self.lo_prev = inside
+        return self.lo_ghost
+
+    def advance_high(self, E):
+        """E_y, E_z ghosts at the new integer step from the last E column."""
+        inside = np.stack([E[1][..., -1:], E[2][..., -1:]])
+        self.hi_ghost = self.hi_prev + self.k * (inside - self.hi_ghost)
+        self.hi_prev = inside
+        return self.hi_ghost
 
 
-def _ghost_B_low(E, B):
-    """B_y and B_z at x index -1 from the first columns."""
-    return 2.0 * E[2][..., :1] - B[1][..., :1], -2.0 * E[1][..., :1] - B[2][..., :1]
-
-
-def curl_E(E, grid, B=None):
-    """curl E at the B positions (B: for the ghosts of an open x axis)."""
+def curl_E(E, grid, ghost=None):
+    """curl E at the B positions (ghost: E_y, E_z beyond an open high x face)."""
     gy = gz = None
     if grid.open_x:
-        gy, gz = _ghost_E_high(E, B)
+        gy, gz = ghost[0], ghost[1]
     return np.stack([
         _dplus(E[2], 1, grid) - _dplus(E[1], 2, grid),
         _dplus(E[0], 2, grid) - _dplus(E[2], 0, grid, gz),
@@ -351,11 +374,11 @@ def curl_E(E, grid, B=None):
     ])
 
 
-def curl_B(B, grid, E=None):
-    """curl B at the E positions (E: for the ghosts of an open x axis)."""
+def curl_B(B, grid, ghost=None):
+    """curl B at the E positions (ghost: B_y, B_z beyond an open low x face)."""
     gy = gz = None
     if grid.open_x:
-        gy, gz = _ghost_B_low(E, B)
+        gy, gz = ghost[0], ghost[1]
     return np.stack([
         _dminus(B[2], 1, grid) - _dminus(B[1], 2, grid),
         _dminus(B[0], 2, grid) - _dminus(B[2], 0, grid, gz),
@@ -368,12 +391,18 @@ def div_E(E, grid):
     return _dminus(E[0], 0, grid) + _dminus(E[1], 1, grid) + _dminus(E[2], 2, grid)
 
 
-def yee_step(E, B, J, grid):
-    """B -= dt/2 curl E; E += dt (curl B - J); B -= dt/2 curl E (in place)."""
+def yee_step(E, B, J, grid, mur=None):
+    """B -= dt/2 curl E; E += dt (curl B - J); B -= dt/2 curl E (in place).
+    With open x faces the ghost columns come from the Mur state ``mur``."""
     dt = grid.dt
-    B -= 0.5 * dt * curl_E(E, grid, B)
-    E += dt * (curl_B(B, grid, E) - J)
-    B -= 0.5 * dt * curl_E(E, grid, B)
+    if not grid.open_x:
+        B -= 0.5 * dt * curl_E(E, grid)
+        E += dt * (curl_B(B, grid) - J)
+        B -= 0.5 * dt * curl_E(E, grid)
+        return
+    B -= 0.5 * dt * curl_E(E, grid, mur.hi_ghost)
+    E += dt * (curl_B(B, grid, mur.advance_low(B)) - J)
+    B -= 0.5 * dt * curl_E(E, grid, mur.advance_high(E))
 
 
 # ---------------------------------------------------------------- Eq. 4
@@ -485,6 +514,7 @@ class Sim:
         self.E = F[0:3].copy()
         self.B = F[3:6].copy()
         self.J = np.zeros((3,) + g.shape)
+        self.mur = MurState(self.E, self.B, g) if g.open_x else None
         self.nstep = 0
         self.residual0 = div_E(self.E, g) - self.rho()
 
@@ -544,7 +574,7 @@ class Sim:
                     x = self.xi[k][:, 0]
                     self._keep(k, (x >= 0.0) & (x < self.grid.n[0]))
             if not self.test_particle:
-                yee_step(self.E, self.B, self.J, self.grid)
+                yee_step(self.E, self.B, self.J, self.grid, self.mur)
             self.nstep += 1
             if self.window is not None:
                 self._advance_window()
@@ -580,6 +610,7 @@ class Sim:
         for F in (self.E, self.B, self.J):
             F[..., :nx - S] = F[..., S:].copy()
             F[..., nx - S:] = 0.0
+        self.mur.reset(self.E, self.B)
         self.shifts += 1
         for k in range(len(self.species)):
             self.xi[k][:, 0] -= S

@@ -65,6 +65,8 @@ DIAG = [
 ]
 
 WINDOW = [
+    TW.test_open_faces_stay_stable,
+    TW.test_oblique_wave_leaves,
     lambda: TW.test_open_faces_absorb_leaving_pulses(1, "y"),
     lambda: TW.test_open_faces_absorb_leaving_pulses(-1, "y"),
     lambda: TW.test_open_faces_absorb_leaving_pulses(1, "z"),
@@ -105,8 +107,8 @@ MUTANTS = [
     ("shape_pair", "k0 = (i0 - b)", "k0 = (i1 - b)", GRID),
     ("shape_pair", "S1[rows, k1] = 1.0 - (p1 - i1)", "S1[rows, k1] = 1.0 - (p0 - i0)", GRID),
     ("charge_density", "(frac[a] if corner[a] else 1.0 - frac[a])", "(1.0 - frac[a] if corner[a] else frac[a])", GRID),
-    ("yee_step", "E += dt * (curl_B(B, grid, E) - J)", "E += dt * (curl_B(B, grid, E) + J)", GRID),
-    ("yee_step", "B -= 0.5 * dt * curl_E(E, grid, B)\n    E +=", "B += 0.5 * dt * curl_E(E, grid, B)\n    E +=", GRID),
+    ("yee_step", "E += dt * (curl_B(B, grid) - J)", "E += dt * (curl_B(B, grid) + J)", GRID),
+    ("yee_step", "B -= 0.5 * dt * curl_E(E, grid)\n        E +=", "B += 0.5 * dt * curl_E(E, grid)\n        E +=", GRID),
     ("curl_E", "_dplus(E[1], 0, grid, gy) - _dplus(E[0], 1, grid)", "_dplus(E[0], 1, grid) - _dplus(E[1], 0, grid, gy)", GRID),
     ("curl_B", "_dminus(B[0], 2, grid) - _dminus(B[2], 0, grid, gz)", "_dminus(B[0], 2, grid) + _dminus(B[2], 0, grid, gz)", GRID),
     ("_dplus", "np.roll(F, -1, axis=AXIS[a])", "np.roll(F, 1, axis=AXIS[a])", GRID),
@@ -115,10 +117,14 @@ MUTANTS = [
     ("wrap", "np.mod(xi[:, a], grid.n[a])", "np.mod(xi[:, a], grid.n[a] - 1)", DIAG),
     ("polarization", "s[selected].sum(axis=0) / N", "s[selected].sum(axis=0) / max(N - 1, 1)", DIAG),
     ("kinetic_energy_mev", "mu * (gamma - 1.0)", "(gamma - 1.0)", DIAG),
-    ("_ghost_E_high", "2.0 * B[2][..., -1:] - E[1][..., -1:]", "2.0 * B[2][..., -1:] + E[1][..., -1:]", WINDOW),
-    ("_ghost_E_high", "-2.0 * B[1][..., -1:] - E[2][..., -1:]", "2.0 * B[1][..., -1:] - E[2][..., -1:]", WINDOW),
-    ("_ghost_B_low", "-2.0 * E[1][..., :1] - B[2][..., :1]", "2.0 * E[1][..., :1] - B[2][..., :1]", WINDOW),
-    ("_ghost_B_low", "2.0 * E[2][..., :1] - B[1][..., :1]", "2.0 * E[2][..., :1] + B[1][..., :1]", WINDOW),
+    ("MurState.advance_low", "self.lo_prev + self.k * (inside - self.lo_ghost)",
+     "self.lo_prev - self.k * (inside - self.lo_ghost)", WINDOW),
+    ("MurState.advance_high", "self.hi_prev + self.k * (inside - self.hi_ghost)",
+     "inside + self.k * (inside - self.hi_ghost)", WINDOW),
+    ("MurState.__init__", "(grid.dt - grid.d[0]) / (grid.dt + grid.d[0])", "0.0", WINDOW),
+    ("MurState.advance_high", "np.stack([E[1][..., -1:], E[2][..., -1:]])",
+     "np.stack([E[2][..., -1:], E[1][..., -1:]])", WINDOW),
+    ("yee_step", "mur.advance_low(B)", "mur.lo_ghost", WINDOW),
     ("_scatter", "(ind[0] < grid.n[0])", "(ind[0] <= grid.n[0])", WINDOW),
     ("interpolate", "inside = (raw >= 0)", "inside = (raw >= -1)", WINDOW),
     ("Sim.step", "(x >= 0.0) & (x < self.grid.n[0])", "(x >= -1.0) & (x < self.grid.n[0])", WINDOW),
@@ -137,7 +143,7 @@ MUTANTS = [
 @pytest.mark.parametrize("fname,old,new,checks", MUTANTS,
                          ids=["%s:%d" % (m[0], i) for i, m in enumerate(MUTANTS)])
 def test_mutant_is_killed(monkeypatch, fname, old, new, checks):
-    owner, name = (O.Sim, fname.split(".")[1]) if fname.startswith("Sim.") else (O, fname)
+    owner, name = (getattr(O, fname.split(".")[0]), fname.split(".")[1]) if "." in fname else (O, fname)
     src = textwrap.dedent(inspect.getsource(getattr(owner, name)))
     assert old in src, "mutation snippet not found in %s" % fname
     glb = dict(O.__dict__)
