@@ -435,12 +435,22 @@ def cpu_baseline_batch(specs, states, budget_s):
                       "pass each, FP64 NumPy, one thread of %s, %.1f s" % (runs, n, cpu_model(), dt)}
 
 
-def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None):
+def window_kw(spec, shift_cells):
+    """A co-moving window at c over the workload's own plasma: the injected
+    density continues the loader's profile (n0, ramped from x = 0)."""
+    pl = spec["plasma"]
+    return dict(speed=1.0, shift_cells=int(shift_cells), ppc=pl["ppc"], n0=pl["n0"], ramp_start=0.0,
+                ramp_len=pl["ramp_len"] if pl["profile"] == "ramp" else 0.0, s0=pl["s0"])
+
+
+def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None, window=False):
     """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
     import torch
     cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile)
     t0 = time.time()
     sim = S.Simulation(cfg, state["particles"], state["fields"])
+    if window:
+        sim.window(**window_kw(spec, sim.stats()["tile"][0]))
     torch.cuda.synchronize()
     print("[bench] %s init (sort + upload) %.1f s" % (precision, time.time() - t0),
           file=sys.stderr, flush=True)
@@ -480,6 +490,9 @@ def main():
                     help="write the push kernel's traffic record from rocprofv3 counter files and exit")
     ap.add_argument("--cpu-sample", type=int, default=8_000_000,
                     help="particles per species in the CPU-baseline sample")
+    ap.add_argument("--window", action="store_true",
+                    help="c1-c3: run with a co-moving window at c (open x faces, injection of the "
+                         "workload's plasma, shift by one tile column)")
     ap.add_argument("--batch-only", action="store_true",
                     help="c5: time the autotuned batch only (no default-tile batch, no sequential runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -538,8 +551,11 @@ def main():
 
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps, tile)
+    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps, tile,
+                                        window=args.window)
     stats = sim.stats()
+    if args.window:
+        npart = stats["particles"]   # injected minus removed since the start
     P, N = sim.polarization()
     print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s N=%d"
           % (args.steps, elapsed, json.dumps(timers), stats, P, N), file=sys.stderr, flush=True)
@@ -568,7 +584,9 @@ def main():
                    "particles": npart, "cells": ncells,
                    "precision": "FP32 particles and push; FP64 fields, currents, reductions"
                                 if precision == "fp32" else "FP64",
-                   "tile": list(stats["tile"])[: spec["ndim"]]},
+                   "tile": list(stats["tile"])[: spec["ndim"]],
+                   **({"moving_window": dict(window_kw(spec, stats["tile"][0]), shifts=stats["shifts"])}
+                      if args.window else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_push_tiles (gather+Boris+T-BMT+move+Esirkepov deposit)",
@@ -585,7 +603,8 @@ def main():
     torch.cuda.synchronize()
 
     if precision == "fp32" and not args.no_fp64_compare:
-        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile)
+        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile,
+                                       window=args.window)
         P64, _ = sim64.polarization()
         sim64.close()
         del sim64

@@ -186,9 +186,62 @@ int pic_energy(pic_ctx* ctx, double* out, int32_t cap);
 
 /* Counters since init: out[0] steps, out[1] particles that changed tile,
  * out[2] particles currently in the overflow store, out[3] repacks done,
- * out[4] total particles; with cap >= 8 also out[5 .. 7] the tile edge in
- * cells per axis in use (1 on axes beyond ndim).  cap >= 5.  Waits. */
+ * out[4] particles in the box; with cap >= 8 also out[5 .. 7] the tile edge
+ * in cells per axis in use (1 on axes beyond ndim); with cap >= 12 also
+ * out[8 .. 11] the particles of each species in the box (what pic_particles
+ * returns); with cap >= 13 also out[12] the moving window's shifts so far.
+ * cap >= 5.  Waits. */
 int pic_stats(pic_ctx* ctx, int64_t* out, int32_t cap);
+
+/* ---------------------------------------------------------------------------
+ * Co-moving window and open x faces (the co-moving frame of the paper's
+ * runs, section 2).
+ *
+ * After pic_window the x axis is open: fields beyond the two x faces read as
+ * zero for the gather, current deposited beyond them is lost, particles that
+ * cross them leave the box, and the Yee update takes its ghost columns (E_y,
+ * E_z beyond the high face, B_y, B_z beyond the low face) from Mur's
+ * first-order absorbing condition: ghost(new) = inside(old) + k (inside(new)
+ * - ghost(old)), k = (c dt - dx)/(c dt + dx), "inside" the column next to
+ * the face.  It returns about 1e-5 of a normally incident pulse's energy and
+ * 1 % at 30 degrees.  The Mur state starts from the first and last columns
+ * at pic_window and again after every shift.  y and z stay periodic.
+ *
+ * The window moves along +x at `speed`: after step n it has travelled
+ * n speed dt (n counted from the pic_window call), and whenever that reaches
+ * another shift_cells cells the box shifts by shift_cells cells: fields and
+ * the last step's current move shift_cells cells towards -x, the first
+ * shift_cells columns of particles leave, and the last shift_cells columns
+ * start with zero fields and cold plasma.  Injection puts ppc particles of
+ * every species into each new cell whose centre (lab frame, x measured from
+ * the box's position at pic_window) sees density
+ *     n(x) = n0 min(1, max(0, (x - ramp_start) / ramp_len))   (ramp_len > 0)
+ *     n(x) = n0 for x >= ramp_start, else 0                    (ramp_len = 0)
+ * with n > 0, at in-cell offset (q + 1/2)/ppc along every axis (q = 0 ..
+ * ppc-1), u = 0, spin s0 and weight n/ppc.  Particle q of column c (0 ..
+ * shift_cells-1 from the first new column) in cell row (y, z) of a species
+ * gets id next + ((z ny + y) shift_cells + c) ppc + q, where next starts at
+ * the species' initial count and advances by nz ny shift_cells ppc per
+ * shift.  Ids of the initial particles are their row indices; pic_particles
+ * returns the particles in the box sorted by id, with positions in box
+ * coordinates.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double speed;          /* window velocity along +x, units of c (0: a fixed box with open x faces) */
+    int32_t shift_cells;   /* cells per shift: a multiple of the tile's x edge, below n[0] */
+    int32_t ppc;           /* injected particles per cell and species, 0 .. 256 (0: none) */
+    double n0;             /* injected density, n_c */
+    double ramp_start;     /* lab-frame x (c/omega0) where the injected density starts */
+    double ramp_len;       /* length of the linear ramp to n0 (c/omega0); 0: a step */
+    double s0[3];          /* injected spin, |s0| = 1 (when ppc > 0) */
+} pic_window_config;
+
+/* Open the x faces and start the window (a later call replaces the
+ * parameters and restarts the travel count).  The reference of the
+ * div E - rho diagnostic is taken again with the open faces.  Errors:
+ * PIC_EINVAL for parameters outside the ranges above, PIC_ECAPACITY when
+ * the ids of injected particles would pass 2^31.  Waits. */
+int pic_window(pic_ctx* ctx, const pic_window_config* w);
 
 /* Per-kernel GPU timing with HIP events on the context's stream.
  * pic_timing(ctx, 1) starts (and resets) recording, 0 stops it.

@@ -227,6 +227,7 @@ public:
     virtual Status stats(int64_t* out, int cap) = 0;
     virtual Status timing(int enable) = 0;
     virtual Status timing_read(double* ms, int64_t* launches, int cap) = 0;
+    virtual Status window(const pic_window_config* w) = 0;
     virtual void release() = 0;
 };
 
@@ -255,9 +256,13 @@ public:
     Status stats(int64_t* out, int cap) override;
     Status timing(int enable) override;
     Status timing_read(double* ms, int64_t* launches, int cap) override;
+    Status window(const pic_window_config* w) override;
     void release() override;
 
 private:
+    Status window_shift();
+    Status live_counts(long long out[kMaxSpecies]);
+    Status grow_stores(long long need);
     // device memory
     void* dalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
@@ -328,6 +333,14 @@ private:
     int32_t* nf_flag_ = nullptr;
     freal* jbuf_[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int jcur_ = 0;                 // buffer holding the last step's current
+    long long store_cap_ = 0;      // slots of the leaver and overflow stores
+    // moving window
+    bool win_on_ = false;
+    pic_window_config win_{};
+    int64_t win_step0_ = 0;        // nstep_ at pic_window
+    long long shifts_ = 0;
+    long long next_id_[kMaxSpecies] = {0, 0, 0, 0};
+    freal* scratch_ = nullptr;     // one field array, for the shifts
     Timer timer_;
 };
 
@@ -456,6 +469,7 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         kf_.cb[a] = 0.5 * dt / d_[a];
         kf_.ce[a] = dt / d_[a];
     }
+    kf_.mur_k = (dt - d_[0]) / (dt + d_[0]);
     for (int s = 0; s < kMaxSpecies; ++s) {
         const bool on = s < c.nspecies;
         const double r = on ? c.sp[s].Z / c.sp[s].mu : 0.0;
@@ -559,10 +573,12 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     // ---- device allocations
     Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
     if (S.code) return S;
-    S = alloc_store(lv_, std::max(npart_, 1LL), true);
+    store_cap_ = std::max(npart_, 1LL);
+    S = alloc_store(lv_, store_cap_, true);
     if (S.code) return S;
-    S = alloc_store(st_, std::max(npart_, 1LL), true);
+    S = alloc_store(st_, store_cap_, true);
     if (S.code) return S;
+    for (int s = 0; s < c.nspecies; ++s) next_id_[s] = count_sp_[s];
     seg_.start = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     seg_.cap = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     seg_.count = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
@@ -716,9 +732,9 @@ Status Engine<real, DIM>::step(int nsteps) {
         tstop(2);
         if (deposit_) {
             tstart(3);
-            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 0, stream_)));
             HIP_OR_FAIL((launch_fdtd_e<freal, DIM>(g_, kf_, f_, jbuf_[jcur_], stream_)));
-            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, stream_)));
+            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 1, stream_)));
             tstop(3);
         }
         HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
@@ -726,6 +742,15 @@ Status Engine<real, DIM>::step(int nsteps) {
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
         ++nstep_;
+        if (win_on_) {
+            // the window has moved (n - n0) speed dt; shift once per whole
+            // shift_cells cells of that (evaluated as written, in FP64)
+            const int S = win_.shift_cells;
+            while ((double)(nstep_ - win_step0_) * win_.speed * R_.cfg.dt >= (double)((shifts_ + 1) * S) * d_[0]) {
+                Status Sx = window_shift();
+                if (Sx.code) return Sx;
+            }
+        }
     }
     return Status{};
 }
@@ -749,6 +774,7 @@ Status Engine<real, DIM>::repack() {
     HIP_OR_FAIL(hipMemcpy(ssp.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<long long> want(cnt.begin(), cnt.end());
     for (int i = 0; i < nst; ++i) {
+        if (scell[i] == kDeadCell) continue;   // left the box: dropped by the insertion below
         int c[3];
         unpack_cell<DIM>(scell[i], c[0], c[1], c[2]);
         const int tile = c[0] / g_.T[0] + g_.nt[0] * (c[1] / g_.T[1] + g_.nt[1] * (c[2] / g_.T[2]));
@@ -966,10 +992,22 @@ Status Engine<real, DIM>::fields(uint32_t mask, double* out, size_t cap) {
 template <typename real, int DIM>
 Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_t* n_out) {
     if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
-    const long long n = count_sp_[species];
+    long long per[kMaxSpecies];
+    Status L = live_counts(per);
+    if (L.code) return L;
+    const long long n = per[species];
     if (n_out) *n_out = n;
     if (cap < (size_t)n * PIC_PARTICLE_OUT_COLS) return fail(PIC_EINVAL, "cap too small for %lld particles", n);
     if (n > 0 && !out) return fail(PIC_EINVAL, "host_out is NULL");
+    // Without a moving window the ids are 0 .. n-1 and row i is particle i;
+    // with one, the rows are gathered first and sorted by id.
+    const bool by_index = !win_on_;
+    std::vector<double> rows;
+    std::vector<long long> ids;
+    if (!by_index) {
+        rows.resize((size_t)n * PIC_PARTICLE_OUT_COLS);
+        ids.reserve((size_t)n);
+    }
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
     std::vector<int32_t> start(nseg_), count(nseg_);
     HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -1002,11 +1040,18 @@ Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_
         }
         for (const auto& r : ranges)
             for (long long q = r.first; q < r.second; ++q) {
-                if (stash && sp[q] != species) continue;
+                if (stash && (sp[q] != species || cell[q] == kDeadCell)) continue;
                 const long long i = id[q];
-                if (i < 0 || i >= n || seen[i]) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (id %lld)", i);
-                seen[i] = 1;
-                double* row = out + i * PIC_PARTICLE_OUT_COLS;
+                double* row;
+                if (by_index) {
+                    if (i < 0 || i >= n || seen[i]) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (id %lld)", i);
+                    seen[i] = 1;
+                    row = out + i * PIC_PARTICLE_OUT_COLS;
+                } else {
+                    if ((long long)ids.size() >= n) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (count)");
+                    row = rows.data() + ids.size() * PIC_PARTICLE_OUT_COLS;
+                    ids.push_back(i);
+                }
                 int c[3];
                 unpack_cell<DIM>(cell[q], c[0], c[1], c[2]);
                 row[0] = (double)i;
@@ -1028,8 +1073,21 @@ Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_
     if (S.code) return S;
     S = emit(st_, nst, {{0, (long long)nst}}, true);
     if (S.code) return S;
-    for (long long i = 0; i < n; ++i)
-        if (!seen[i]) return fail(PIC_ESTATE, "particle %lld of species %d is missing", i, species);
+    if (by_index) {
+        for (long long i = 0; i < n; ++i)
+            if (!seen[i]) return fail(PIC_ESTATE, "particle %lld of species %d is missing", i, species);
+        return Status{};
+    }
+    if ((long long)ids.size() != n) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (count)");
+    std::vector<long long> order((size_t)n);
+    for (long long q = 0; q < n; ++q) order[q] = q;
+    std::sort(order.begin(), order.end(), [&](long long a, long long b) { return ids[a] < ids[b]; });
+    for (long long q = 0; q < n; ++q) {
+        if (q > 0 && ids[order[q]] == ids[order[q - 1]])
+            return fail(PIC_ESTATE, "particle id %lld appears twice", ids[order[q]]);
+        std::memcpy(out + q * PIC_PARTICLE_OUT_COLS, rows.data() + order[q] * PIC_PARTICLE_OUT_COLS,
+                    PIC_PARTICLE_OUT_COLS * sizeof(double));
+    }
     return Status{};
 }
 
@@ -1084,12 +1142,175 @@ Status Engine<real, DIM>::stats(int64_t* out, int cap) {
     int32_t nst = 0;
     HIP_OR_FAIL(hipMemcpy(&moved, moved_, sizeof moved, hipMemcpyDeviceToHost));
     HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    long long per[kMaxSpecies];
+    Status S = live_counts(per);
+    if (S.code) return S;
+    long long total = 0;
+    for (int s = 0; s < g_.nsp; ++s) total += per[s];
     out[0] = nstep_;
     out[1] = (int64_t)moved;
     out[2] = nst;
     out[3] = repacks_;
-    out[4] = npart_;
+    out[4] = total;
     for (int a = 0; a < 3 && 5 + a < cap; ++a) out[5 + a] = g_.T[a];
+    for (int s = 0; s < kMaxSpecies && 8 + s < cap; ++s) out[8 + s] = per[s];
+    if (cap > 12) out[12] = shifts_;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::live_counts(long long out[kMaxSpecies]) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    for (int s = 0; s < kMaxSpecies; ++s) out[s] = 0;
+    std::vector<int32_t> cnt(nseg_);
+    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int sg = 0; sg < nseg_; ++sg) out[sg % g_.nsp] += cnt[sg];
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    if (nst > 0) {
+        std::vector<int32_t> cell(nst), sp(nst);
+        HIP_OR_FAIL(hipMemcpy(cell.data(), st_.cell, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(sp.data(), st_.sp, nst * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int i = 0; i < nst; ++i)
+            if (cell[i] != kDeadCell) out[sp[i]]++;
+    }
+    return Status{};
+}
+
+// The leaver and overflow stores must hold every particle of the box (all
+// may leave their tile in one step); injection can raise that number.  Both
+// are empty between steps, so they are replaced without copying.
+template <typename real, int DIM>
+Status Engine<real, DIM>::grow_stores(long long need) {
+    if (need <= store_cap_) return Status{};
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    if (nst != 0) return fail(PIC_ESTATE, "overflow store not empty when growing it");
+    const long long cap = need + need / 4;
+    free_store(lv_);
+    free_store(st_);
+    Status S = alloc_store(lv_, cap, true);
+    if (S.code) return S;
+    S = alloc_store(st_, cap, true);
+    if (S.code) return S;
+    store_cap_ = cap;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::window(const pic_window_config* w) {
+    if (!w) return fail(PIC_EINVAL, "window config is NULL");
+    if (!(w->speed >= 0.0) || !std::isfinite(w->speed)) return fail(PIC_EINVAL, "window speed must be >= 0");
+    if (w->shift_cells < 1 || w->shift_cells >= g_.n[0] || w->shift_cells % g_.T[0] != 0)
+        return fail(PIC_EINVAL, "shift_cells = %d must be a multiple of the tile's x edge %d and below n[0] = %d",
+                    w->shift_cells, g_.T[0], g_.n[0]);
+    if (w->ppc < 0 || w->ppc > 256) return fail(PIC_EINVAL, "ppc = %d outside 0 .. 256", w->ppc);
+    if (!(w->n0 >= 0.0) || !std::isfinite(w->n0) || !(w->ramp_len >= 0.0) || !std::isfinite(w->ramp_len) ||
+        !std::isfinite(w->ramp_start))
+        return fail(PIC_EINVAL, "n0 and ramp_len must be finite and >= 0, ramp_start finite");
+    if (w->ppc > 0) {
+        const double s2 = w->s0[0] * w->s0[0] + w->s0[1] * w->s0[1] + w->s0[2] * w->s0[2];
+        if (!(std::fabs(s2 - 1.0) <= 1e-6)) return fail(PIC_EINVAL, "|s0| must be 1");
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    if (!scratch_) {
+        scratch_ = (freal*)dalloc(g_.ncells * sizeof(freal));
+        f_.mur = (freal*)dalloc((size_t)MUR_COLUMNS * g_.n[1] * g_.n[2] * sizeof(freal));
+        if (!scratch_ || !f_.mur) return fail(PIC_ENOMEM, "device allocation failed");
+    }
+    win_ = *w;
+    win_on_ = true;
+    win_step0_ = nstep_;
+    shifts_ = 0;
+    g_.open_x = 1;
+    HIP_OR_FAIL((launch_mur_reset<freal, DIM>(g_, f_, stream_)));
+    // div E - rho reference with the open faces
+    Status S = compute_rho();
+    if (S.code) return S;
+    Vec3d inv;
+    for (int a = 0; a < 3; ++a) inv.v[a] = 1.0 / d_[a];
+    HIP_OR_FAIL((launch_div_residual<freal, DIM>(g_, inv, f_, rho_, ref_, ref_, blockmax_, resid_blocks_, stream_)));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    return Status{};
+}
+
+// One shift of the moving window by S = shift_cells cells (a whole number k
+// of tile columns): the overflow store is folded back first, every field
+// array moves S cells towards -x, the segment table rotates by k tile
+// columns (the first k columns' segments, whose particles leave the box,
+// become the last k columns' with count 0), the kept particles move S cells
+// down in x, and cold plasma is injected into the last S columns.
+template <typename real, int DIM>
+Status Engine<real, DIM>::window_shift() {
+    const int S = win_.shift_cells;
+    const int k = S / g_.T[0];
+    Status St = repack();   // waits; empties the overflow store
+    if (St.code) return St;
+    // fields and the last step's current
+    freal** arrs[9] = {&f_.E[0], &f_.E[1], &f_.E[2], &f_.B[0], &f_.B[1], &f_.B[2],
+                       &jbuf_[jcur_][0], &jbuf_[jcur_][1], &jbuf_[jcur_][2]};
+    for (freal** a : arrs) {
+        HIP_OR_FAIL((launch_shift_x<freal>(g_, *a, scratch_, S, stream_)));
+        std::swap(*a, scratch_);
+    }
+    for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
+    HIP_OR_FAIL((launch_mur_reset<freal, DIM>(g_, f_, stream_)));
+    // segment table
+    std::vector<int32_t> start(nseg_), cap(nseg_), cnt(nseg_);
+    HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(cap.data(), seg_.cap, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> nstart(nseg_), ncap(nseg_), ncnt(nseg_);
+    const int ntx = g_.nt[0];
+    for (int t = 0; t < g_.ntiles; ++t) {
+        const int tx = t % ntx;
+        const bool kept = tx < ntx - k;
+        const int src_t = t - tx + (kept ? tx + k : tx - (ntx - k));
+        for (int sp = 0; sp < g_.nsp; ++sp) {
+            const int d = t * g_.nsp + sp, s = src_t * g_.nsp + sp;
+            nstart[d] = start[s];
+            ncap[d] = cap[s];
+            ncnt[d] = kept ? cnt[s] : 0;
+        }
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, ncap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(seg_.count, ncnt.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL((launch_shift_cells<real, DIM>(p_, seg_, S, nseg_, stream_)));
+    // injection
+    long long live = 0;
+    for (int d = 0; d < nseg_; ++d) live += ncnt[d];
+    const int nz = DIM == 3 ? g_.n[2] : 1;
+    const long long per_sp = (long long)nz * g_.n[1] * S * win_.ppc;
+    shifts_++;
+    if (win_.ppc > 0) {
+        St = grow_stores(live + per_sp * g_.nsp);
+        if (St.code) return St;
+        InjectArgs a{};
+        a.S = S;
+        a.ppc = win_.ppc;
+        a.origin = shifts_ * S;
+        a.dx = d_[0];
+        a.n0 = win_.n0;
+        a.ramp_start = win_.ramp_start;
+        a.ramp_len = win_.ramp_len;
+        for (int c = 0; c < 3; ++c) a.s0[c] = win_.s0[c];
+        for (int sp = 0; sp < g_.nsp; ++sp) {
+            if (next_id_[sp] + per_sp > (1LL << 31) - 1)
+                return fail(PIC_ECAPACITY, "particle ids of species %d would pass 2^31", sp);
+            a.next_id[sp] = (int32_t)next_id_[sp];
+            next_id_[sp] += per_sp;
+        }
+        HIP_OR_FAIL((launch_inject<real, DIM>(g_, p_, seg_, st_, ctr_, a, stream_)));
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    long long per[kMaxSpecies];
+    St = live_counts(per);
+    if (St.code) return St;
+    npart_ = 0;
+    for (int s = 0; s < g_.nsp; ++s) npart_ += per[s];
     return Status{};
 }
 
@@ -1957,6 +2178,11 @@ int pic_energy(pic_ctx* ctx, double* out, int32_t cap) {
 int pic_stats(pic_ctx* ctx, int64_t* out, int32_t cap) {
     CTX_CHECK(ctx);
     return finish(ctx, ctx->eng->stats(out, cap));
+}
+
+int pic_window(pic_ctx* ctx, const pic_window_config* w) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->window(w));
 }
 
 int pic_timing(pic_ctx* ctx, int32_t enable) {

@@ -35,7 +35,14 @@ struct Fields {
     real* E[3];
     real* B[3];
     real* J[3];
+    // Mur state of open x faces (NULL when periodic), 8 columns of ny nz
+    // values: E_y, E_z ghosts beyond the high face, E_y, E_z of the last
+    // column, B_y, B_z ghosts beyond the low face, B_y, B_z of the first
+    // column, each at its last time level
+    real* mur;
 };
+
+enum MurColumn { MUR_HI_GHOST = 0, MUR_HI_PREV = 2, MUR_LO_GHOST = 4, MUR_LO_PREV = 6, MUR_COLUMNS = 8 };
 
 struct Geom {
     int ndim;
@@ -45,7 +52,12 @@ struct Geom {
     int nt[3];      // tiles per axis
     int ntiles;
     long long ncells;
+    int open_x;     // x faces open (moving window): no wrap along x
 };
+
+// Cell word of a particle that left the box through an open x face: it is
+// dropped by the leaver insertion and skipped everywhere else.
+constexpr int32_t kDeadCell = -1;
 
 template <typename real>
 struct Consts {
@@ -58,6 +70,7 @@ struct Consts {
     real Z[kMaxSpecies];
     real cb[3];       // (dt / 2) / d_a  (B half step)
     real ce[3];       // dt / d_a        (E step)
+    real mur_k;       // (c dt - dx) / (c dt + dx), Mur's coefficient at open x faces
 };
 
 struct Segs {
@@ -208,12 +221,15 @@ __device__ inline real interp(const TileFields<real, DIM>& F, int c,
     return lerp(a0, a1, fz);
 }
 
-// Field source in global memory with periodic wrap; cells are absolute.
+// Field source in global memory with periodic wrap (or zero beyond open x
+// faces); cells are absolute.
 template <typename freal, int DIM>
 struct GlobalFields {
     const freal* c[6];
     int n[3];
+    int open_x;
     __device__ inline freal at(int comp, int i, int j, int k) const {
+        if (open_x && (i < 0 || i >= n[0])) return freal(0);
         i = wrap_index(i, n[0]);
         j = wrap_index(j, n[1]);
         k = DIM == 3 ? wrap_index(k, n[2]) : 0;

@@ -11,7 +11,8 @@ constexpr int kFx = 64, kFy = 4;   // field kernels: 64 x 4 threads, x fastest
 // B_z at (i+1/2, j+1/2, k); E_a at half a cell along a.  Forward differences
 // with periodic wrap.  In 2D every d/dz is zero.
 template <typename real, int DIM>
-__device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, int i, int j, int kz) {
+__device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, int i, int j, int kz,
+                                 bool update_hi) {
     const int nx = g.n[0], ny = g.n[1];
     const long long nxy = (long long)nx * ny;
     const long long c = kz * nxy + (long long)j * nx + i;
@@ -21,9 +22,32 @@ __device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fie
     const real* __restrict__ Ey = f.E[1];
     const real* __restrict__ Ez = f.E[2];
     const real ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    // E_y and E_z one cell along +x; beyond an open high x face, the Mur
+    // ghosts, advanced first in the second half step (E then holds the new
+    // step's values): ghost = last(old) + k (last(new) - ghost(old))
+    real eyp, ezp;
+    if (g.open_x && i + 1 == nx) {
+        const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
+        real* m = f.mur + ((long long)kz * g.n[1] + j);
+        real gy = m[MUR_HI_GHOST * nrow], gz = m[(MUR_HI_GHOST + 1) * nrow];
+        if (update_hi) {
+            const real py = m[MUR_HI_PREV * nrow], pz = m[(MUR_HI_PREV + 1) * nrow];
+            gy = py + k.mur_k * (ey - gy);
+            gz = pz + k.mur_k * (ez - gz);
+            m[MUR_HI_GHOST * nrow] = gy;
+            m[(MUR_HI_GHOST + 1) * nrow] = gz;
+            m[MUR_HI_PREV * nrow] = ey;
+            m[(MUR_HI_PREV + 1) * nrow] = ez;
+        }
+        eyp = gy;
+        ezp = gz;
+    } else {
+        eyp = Ey[ip];
+        ezp = Ez[ip];
+    }
     real cx = k.cb[1] * (Ez[jp] - ez);                 // d/dy E_z
-    real cy = -k.cb[0] * (Ez[ip] - ez);                // -d/dx E_z
-    const real cz = k.cb[0] * (Ey[ip] - ey) - k.cb[1] * (Ex[jp] - ex);
+    real cy = -k.cb[0] * (ezp - ez);                   // -d/dx E_z
+    const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (Ex[jp] - ex);
     if (DIM == 3) {
         const long long kp = kz + 1 == g.n[2] ? c - kz * nxy : c + nxy;
         cx -= k.cb[2] * (Ey[kp] - ey);                 // -d/dz E_y
@@ -36,11 +60,11 @@ __device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fie
 
 template <typename real, int DIM>
 __global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_b(Geom g, Consts<real> k, Fields<real> f) {
+k_fdtd_b(Geom g, Consts<real> k, Fields<real> f, int update_hi) {
     const int i = blockIdx.x * kFx + threadIdx.x;
     const int j = blockIdx.y * kFy + threadIdx.y;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    fdtd_b_at<real, DIM>(g, k, f, i, j, blockIdx.z);
+    fdtd_b_at<real, DIM>(g, k, f, i, j, blockIdx.z, update_hi != 0);
 }
 
 // E += dt (curl B - J).  Backward differences with periodic wrap.  The
@@ -62,9 +86,28 @@ __device__ inline void fdtd_e_at(const Geom& g, const Consts<real>& k, const Fie
     const real* __restrict__ By = f.B[1];
     const real* __restrict__ Bz = f.B[2];
     const real bx = Bx[c], by = By[c], bz = Bz[c];
+    // B_y and B_z one cell along -x; beyond an open low x face, the Mur
+    // ghosts advanced to this half step: ghost = first(old) + k (first(new)
+    // - ghost(old))
+    real bym, bzm;
+    if (g.open_x && i == 0) {
+        const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
+        real* m = f.mur + ((long long)kz * g.n[1] + j);
+        const real gy = m[MUR_LO_GHOST * nrow], gz = m[(MUR_LO_GHOST + 1) * nrow];
+        const real py = m[MUR_LO_PREV * nrow], pz = m[(MUR_LO_PREV + 1) * nrow];
+        bym = py + k.mur_k * (by - gy);
+        bzm = pz + k.mur_k * (bz - gz);
+        m[MUR_LO_GHOST * nrow] = bym;
+        m[(MUR_LO_GHOST + 1) * nrow] = bzm;
+        m[MUR_LO_PREV * nrow] = by;
+        m[(MUR_LO_PREV + 1) * nrow] = bz;
+    } else {
+        bym = By[im];
+        bzm = Bz[im];
+    }
     real cx = k.ce[1] * (bz - Bz[jm]);                 // d/dy B_z
-    real cy = -k.ce[0] * (bz - Bz[im]);                // -d/dx B_z
-    const real cz = k.ce[0] * (by - By[im]) - k.ce[1] * (bx - Bx[jm]);
+    real cy = -k.ce[0] * (bz - bzm);                   // -d/dx B_z
+    const real cz = k.ce[0] * (by - bym) - k.ce[1] * (bx - Bx[jm]);
     if (DIM == 3) {
         const long long km = kz == 0 ? c + (g.n[2] - 1) * nxy : c - nxy;
         cx -= k.ce[2] * (by - By[km]);                 // -d/dz B_y
@@ -89,10 +132,32 @@ k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
     fdtd_e_at<real, DIM>(g, k, f, jclear, i, j, blockIdx.z);
 }
 
+// Moving window: dst = src moved S cells towards -x, zero in the last S columns.
+template <typename freal>
+__global__ void __launch_bounds__(kBlock)
+k_shift_x(Geom g, const freal* __restrict__ src, freal* __restrict__ dst, int S) {
+    const int nx = g.n[0];
+    for (long long c = blockIdx.x * (long long)kBlock + threadIdx.x; c < g.ncells;
+         c += (long long)gridDim.x * kBlock) {
+        const int i = (int)(c % nx);
+        dst[c] = i < nx - S ? src[c + S] : freal(0);
+    }
+}
+
+template <typename freal>
+hipError_t launch_shift_x(const Geom& g, const freal* src, freal* dst, int S, hipStream_t stream) {
+    long long blocks = (g.ncells + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL((k_shift_x<freal>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, g, src, dst, S);
+    return hipGetLastError();
+}
+template hipError_t launch_shift_x<double>(const Geom&, const double*, double*, int, hipStream_t);
+
 // Batches of 2D runs: run blockIdx.z, its cells at its offset.
 template <typename real>
 __device__ inline Fields<freal> offset_fields(const Fields<freal>& f, long long off) {
     Fields<freal> r;
+    r.mur = nullptr;   // runs of a batch are periodic
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         r.E[c] = f.E[c] + off;
@@ -122,7 +187,7 @@ k_fdtd_b_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict
     int run, i, j;
     if (!batch_cell(runs, blk_run, run, i, j)) return;
     const RunDesc<real>& rd = runs[run];
-    fdtd_b_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), i, j, 0);
+    fdtd_b_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), i, j, 0, false);
 }
 
 template <typename real>
@@ -200,13 +265,17 @@ __device__ inline void reduce_one(int mode, const PArrays<real>& p, long long i,
         for (int corner = 0; corner < (1 << DIM); ++corner) {
             double wgt = q;
             int idx[3] = {0, 0, 0};
+            bool inside = true;
             for (int a = 0; a < DIM; ++a) {
                 const int up = (corner >> a) & 1;
                 wgt *= up ? o[a] : 1.0 - o[a];
                 idx[a] = c[a] + up;
-                if (idx[a] >= g.n[a]) idx[a] -= g.n[a];
+                if (idx[a] >= g.n[a]) {
+                    idx[a] -= g.n[a];
+                    if (a == 0 && g.open_x) inside = false;   // beyond an open x face
+                }
             }
-            atomicAdd(rho + ((long long)idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0], wgt);
+            if (inside) atomicAdd(rho + ((long long)idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0], wgt);
         }
     }
 }
@@ -229,6 +298,7 @@ k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st
         const int n = ctr[CTR_STASH];
         const int b = blockIdx.x - nseg, nb = gridDim.x - nseg;
         for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+            if (st.cell[i] == kDeadCell) continue;   // left the box
             const int tag = st.sp[i];   // run * kMaxSpecies + species
             if (tag / kMaxSpecies != ra.run) continue;
             reduce_one<real, DIM>(mode, st, i, tag % kMaxSpecies, g, ra, v, rho);
@@ -309,6 +379,7 @@ k_bin_particles(Geom g, PArrays<real> p, Segs seg, PArrays<real> st, const int32
     }
     const int nst = ctr[CTR_STASH];
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < nst; i += gridDim.x * kBlock) {
+        if (st.cell[i] == kDeadCell) continue;   // left the box
         const int sp = st.sp[i];
         if (ba.species >= 0 && sp != ba.species) continue;
         bin_one<real, DIM>(st, i, sp, ba, hist, out);
@@ -353,7 +424,8 @@ k_div_residual(Geom g, Vec3d inv_d, Fields<real> f, const double* rho, const dou
         const int i = (int)(rem - (long long)j * nx);
         const long long im = i == 0 ? c + nx - 1 : c - 1;
         const long long jm = j == 0 ? c + (long long)(ny - 1) * nx : c - nx;
-        double div = ((double)f.E[0][c] - (double)f.E[0][im]) * inv_d.v[0]
+        const double exm = (g.open_x && i == 0) ? 0.0 : (double)f.E[0][im];   // zero beyond an open face
+        double div = ((double)f.E[0][c] - exm) * inv_d.v[0]
                    + ((double)f.E[1][c] - (double)f.E[1][jm]) * inv_d.v[1];
         if (DIM == 3) {
             const long long km = kz == 0 ? c + (g.n[2] - 1) * nxy : c - nxy;
@@ -389,9 +461,36 @@ static dim3 field_grid(const Geom& g) {
 }
 
 template <typename real, int DIM>
-hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f, int update_hi,
                          hipStream_t stream) {
-    hipLaunchKernelGGL((k_fdtd_b<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f);
+    hipLaunchKernelGGL((k_fdtd_b<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f, update_hi);
+    return hipGetLastError();
+}
+
+// Mur state of open x faces from the current fields: every ghost and
+// previous value starts as the first (low face) or last (high face) column.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_mur_reset(Geom g, Fields<real> f) {
+    const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    for (long long row = blockIdx.x * (long long)kBlock + threadIdx.x; row < nrow;
+         row += (long long)gridDim.x * kBlock) {
+        const long long first = row * g.n[0], last = first + g.n[0] - 1;
+        for (int c = 0; c < 2; ++c) {
+            const real e = f.E[1 + c][last], b = f.B[1 + c][first];
+            f.mur[(MUR_HI_GHOST + c) * nrow + row] = e;
+            f.mur[(MUR_HI_PREV + c) * nrow + row] = e;
+            f.mur[(MUR_LO_GHOST + c) * nrow + row] = b;
+            f.mur[(MUR_LO_PREV + c) * nrow + row] = b;
+        }
+    }
+}
+
+template <typename real, int DIM>
+hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t stream) {
+    const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    const long long blocks = std::min<long long>((nrow + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL((k_mur_reset<real, DIM>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, g, f);
     return hipGetLastError();
 }
 
@@ -486,7 +585,9 @@ hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStr
 
 #define SPINPIC_INST_GRID(DIM)                                                                 \
     template hipError_t launch_fdtd_b<double, DIM>(const Geom&, const Consts<double>&,        \
-                                                   const Fields<double>&, hipStream_t);        \
+                                                   const Fields<double>&, int, hipStream_t);   \
+    template hipError_t launch_mur_reset<double, DIM>(const Geom&, const Fields<double>&,     \
+                                                      hipStream_t);                            \
     template hipError_t launch_fdtd_e<double, DIM>(const Geom&, const Consts<double>&,        \
                                                    const Fields<double>&, double* const*,      \
                                                    hipStream_t);                               \

@@ -79,11 +79,37 @@ template <typename real>
 hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
                                const Fields<freal>& f, freal* const* jclear, hipStream_t stream);
 
+// Moving window.  A shift moves the box S cells along +x: every field array
+// shifts S cells towards -x with zeros in the last S columns (dst must not
+// alias src), the particles of the kept segments move S cells down in x,
+// and cold plasma is injected into the last S columns.
+struct InjectArgs {
+    int S;                 // columns injected: the last S of the box
+    int ppc;               // particles per cell and species
+    long long origin;      // cells from the lab-frame origin to the box's first cell
+    double dx;
+    double n0, ramp_start, ramp_len;   // lab-frame density: n0 times a ramp (a step if ramp_len is 0)
+    double s0[3];
+    int32_t next_id[kMaxSpecies];      // id of the species' first particle of this shift
+};
+template <typename freal>
+hipError_t launch_shift_x(const Geom& g, const freal* src, freal* dst, int S, hipStream_t stream);
+template <typename real, int DIM>
+hipError_t launch_shift_cells(const PArrays<real>& p, const Segs& seg, int S, int nseg, hipStream_t stream);
+template <typename real, int DIM>
+hipError_t launch_inject(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
+                         int32_t* ctr, const InjectArgs& a, hipStream_t stream);
+
 // Yee update: B -= (dt/2) curl E, or E += dt (curl B - J) while zeroing the
 // three current arrays jclear (may be NULL).
+// update_hi: the second B half step of a step, which first advances the
+// Mur ghosts of an open high x face (E holds the new step's values).
 template <typename real, int DIM>
-hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f,
+hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f, int update_hi,
                          hipStream_t stream);
+// Mur state of open x faces (f.mur) started from the current fields.
+template <typename real, int DIM>
+hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t stream);
 template <typename real, int DIM>
 hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
                          real* const* jclear, hipStream_t stream);

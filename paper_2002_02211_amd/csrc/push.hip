@@ -23,18 +23,21 @@ struct TileJ {
     }
 };
 
-// Current sink straight into global J with periodic wrap.
+// Current sink straight into global J with periodic wrap (current beyond
+// open x faces is dropped).
 template <typename freal, int DIM>
 struct GlobalJ {
     freal* J[3];
     int n[3];
     int b[3];  // absolute base node
+    int open_x;
     template <typename real>
     __device__ inline void add_nz(int c, int i, int j, int k, real v) const {
         if (v != real(0)) add(c, i, j, k, v);
     }
     template <typename real>
     __device__ inline void add(int c, int i, int j, int k, real v) const {
+        if (open_x && (b[0] + i < 0 || b[0] + i >= n[0])) return;
         const int ix = wrap_index(b[0] + i, n[0]);
         const int iy = wrap_index(b[1] + j, n[1]);
         const int iz = DIM == 3 ? wrap_index(b[2] + k, n[2]) : 0;
@@ -142,6 +145,8 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
         const int r0 = threadIdx.x / Gx;
         const int gx = threadIdx.x - r0 * Gx;
         const long long ix = wrap_near(org[0] - 1 + gx, g.n[0]);
+        // beyond an open x face the fields are zero
+        const bool xin = !g.open_x || (org[0] - 1 + gx >= 0 && org[0] - 1 + gx < g.n[0]);
         const int rows = Gy * Gz;
         if (r0 < rpp) {
             for (int rb = r0; rb < rows; rb += kStageRows * rpp) {
@@ -156,8 +161,8 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                         const long long gi = (iz * g.n[1] + iy) * g.n[0] + ix;
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
-                            v[q][c] = f.E[c][gi];
-                            v[q][3 + c] = f.B[c][gi];
+                            v[q][c] = xin ? f.E[c][gi] : freal(0);
+                            v[q][3 + c] = xin ? f.B[c][gi] : freal(0);
                         }
                     }
                 }
@@ -264,6 +269,9 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                 }
                 if (dc[0] | dc[1] | dc[2]) {
                     int nc[3];
+                    // through an open x face the particle leaves the box: a
+                    // leaver whose cell word marks it dead
+                    const bool dead = g.open_x && (c[0] + dc[0] < 0 || c[0] + dc[0] >= g.n[0]);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         nc[a] = c[a];
@@ -276,7 +284,8 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                             if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
                         }
                     }
-                    newcell = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+                    newcell = dead ? kDeadCell : pack_cell<DIM>(nc[0], nc[1], nc[2]);
+                    leave = leave || dead;
                 }
             }
 
@@ -374,7 +383,9 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
         const int r0 = threadIdx.x / Hx;
         const int hx = threadIdx.x - r0 * Hx;
         const long long ix = wrap_near(org[0] - 1 + hx, g.n[0]);
-        if (r0 < rpp) {
+        // current beyond an open x face is dropped
+        const bool xin = !g.open_x || (org[0] - 1 + hx >= 0 && org[0] - 1 + hx < g.n[0]);
+        if (r0 < rpp && xin) {
             for (int hz = 0; hz < Hz; ++hz) {
                 const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + hz, g.n[2]) : 0;
                 for (int hy = r0; hy < Hy; hy += rpp) {
@@ -413,6 +424,8 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
 template <typename real, int DIM>
 __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, const PArrays<real>& st, int i,
                                       int sp, const Fields<freal>& f, int deposit) {
+    const int32_t cell = st.cell[i];
+    if (cell == kDeadCell) return;   // left the box earlier
     GlobalFields<freal, DIM> GF;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -421,9 +434,10 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) GF.n[a] = g.n[a];
+    GF.open_x = g.open_x;
     const real half_dt = real(0.5) * k.dt;
     int c[3];
-    unpack_cell<DIM>(st.cell[i], c[0], c[1], c[2]);
+    unpack_cell<DIM>(cell, c[0], c[1], c[2]);
     real o[3] = {real(0), real(0), real(0)}, u[3], s[3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) o[a] = st.off[a][i];
@@ -457,6 +471,7 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
             sink.n[a] = g.n[a];
             sink.b[a] = 0;
         }
+        sink.open_x = g.open_x;
         const real Z = k.Z[sp];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -466,6 +481,7 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
         esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
     }
     int nc[3];
+    const bool dead = g.open_x && (c[0] + dc[0] < 0 || c[0] + dc[0] >= g.n[0]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         nc[a] = c[a] + dc[a];
@@ -474,7 +490,7 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
             if (nc[a] >= g.n[a]) nc[a] -= g.n[a];
         }
     }
-    st.cell[i] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+    st.cell[i] = dead ? kDeadCell : pack_cell<DIM>(nc[0], nc[1], nc[2]);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) st.off[a][i] = o[a];
 #pragma unroll
@@ -502,8 +518,10 @@ k_insert(Geom g, PArrays<real> p, Segs seg, PArrays<real> lv, PArrays<real> st,
     const int L = ctr[slot];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(moved, (unsigned long long)L);
     for (int q = blockIdx.x * kBlock + threadIdx.x; q < L; q += gridDim.x * kBlock) {
+        const int32_t cell = lv.cell[q];
+        if (cell == kDeadCell) continue;   // left the box: dropped
         int c[3];
-        unpack_cell<DIM>(lv.cell[q], c[0], c[1], c[2]);
+        unpack_cell<DIM>(cell, c[0], c[1], c[2]);
         const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1] + (DIM == 3 ? g.nt[1] * (c[2] / g.T[2]) : 0));
         const int sp = lv.sp[q];
         const int sid = tile * g.nsp + sp;
@@ -537,6 +555,7 @@ k_repack_segments(PArrays<real> from, PArrays<real> to, const int32_t* __restric
 template <typename real>
 __device__ inline Fields<freal> run_fields(const Fields<freal>& f, long long off) {
     Fields<freal> r;
+    r.mur = nullptr;   // runs of a batch are periodic
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         r.E[c] = f.E[c] + off;
@@ -620,7 +639,102 @@ k_insert_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> p, Segs seg
     }
 }
 
+// ---------------------------------------------------------------- moving window
+
+// After the segment table has been rotated by whole tile columns, every
+// particle of a kept segment moves S cells down in x (one workgroup per
+// segment; the segments that left the box have count 0).
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_shift_cells(PArrays<real> p, Segs seg, int S) {
+    const int sid = blockIdx.x;
+    const long long start = seg.start[sid];
+    const int n = seg.count[sid];
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        int c[3];
+        unpack_cell<DIM>(p.cell[start + i], c[0], c[1], c[2]);
+        p.cell[start + i] = pack_cell<DIM>(c[0] - S, c[1], c[2]);
+    }
+}
+
+// Cold plasma in the last S columns: thread idx is particle q of column col,
+// row (cy, cz), species sp, with idx = (((sp nz + cz) ny + cy) S + col) ppc + q.
+// A cell whose centre sees no density (lab frame) gets no particles.  Each
+// particle takes the next slot of its tile's segment, or one in the overflow
+// store when the segment is full.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_inject(Geom g, PArrays<real> p, Segs seg, PArrays<real> st, int32_t* __restrict__ ctr, InjectArgs a) {
+#pragma clang fp contract(off)
+    const int nz = DIM == 3 ? g.n[2] : 1;
+    const long long per_sp = (long long)nz * g.n[1] * a.S * a.ppc;
+    const long long total = per_sp * g.nsp;
+    for (long long idx = blockIdx.x * (long long)kBlock + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * kBlock) {
+        const int sp = (int)(idx / per_sp);
+        const long long in_sp = idx - sp * per_sp;
+        long long r = in_sp;
+        const int q = (int)(r % a.ppc);
+        r /= a.ppc;
+        const int col = (int)(r % a.S);
+        r /= a.S;
+        const int cy = (int)(r % g.n[1]);
+        const int cz = (int)(r / g.n[1]);
+        const int cx = g.n[0] - a.S + col;
+        const double x = ((double)cx + 0.5 + (double)a.origin) * a.dx;
+        double dens;
+        if (a.ramp_len > 0.0) {
+            double v = (x - a.ramp_start) / a.ramp_len;
+            v = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+            dens = a.n0 * v;
+        } else {
+            dens = x >= a.ramp_start ? a.n0 : 0.0;
+        }
+        if (!(dens > 0.0)) continue;
+        const real off = (real)(((double)q + 0.5) / (double)a.ppc);
+        const int tile = cx / g.T[0] + g.nt[0] * (cy / g.T[1] + (DIM == 3 ? g.nt[1] * (cz / g.T[2]) : 0));
+        const int sid = tile * g.nsp + sp;
+        const int pos = atomicAdd(&seg.count[sid], 1);
+        const PArrays<real>* to = &p;
+        long long j;
+        if (pos < seg.cap[sid]) {
+            j = (long long)seg.start[sid] + pos;
+        } else {
+            atomicSub(&seg.count[sid], 1);
+            j = atomicAdd(&ctr[CTR_STASH], 1);
+            to = &st;
+            st.sp[j] = sp;
+        }
+        to->cell[j] = pack_cell<DIM>(cx, cy, cz);
+        for (int d = 0; d < DIM; ++d) to->off[d][j] = off;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            to->u[d][j] = real(0);
+            to->s[d][j] = (real)a.s0[d];
+        }
+        to->w[j] = (real)(dens / (double)a.ppc);
+        to->id[j] = a.next_id[sp] + (int32_t)in_sp;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+
+template <typename real, int DIM>
+hipError_t launch_shift_cells(const PArrays<real>& p, const Segs& seg, int S, int nseg, hipStream_t stream) {
+    hipLaunchKernelGGL((k_shift_cells<real, DIM>), dim3(nseg), dim3(kBlock), 0, stream, p, seg, S);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_inject(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
+                         int32_t* ctr, const InjectArgs& a, hipStream_t stream) {
+    const long long total = (long long)(DIM == 3 ? g.n[2] : 1) * g.n[1] * a.S * a.ppc * g.nsp;
+    if (total <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((total + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL((k_inject<real, DIM>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, g, p, seg, st,
+                       ctr, a);
+    return hipGetLastError();
+}
 
 template <typename real>
 hipError_t launch_repack_segments(const PArrays<real>& from, const PArrays<real>& to,
@@ -686,6 +800,16 @@ hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p
                        slot, moved);
     return hipGetLastError();
 }
+
+#define SPINPIC_WINDOW_INST(real, DIM)                                                                        \
+    template hipError_t launch_shift_cells<real, DIM>(const PArrays<real>&, const Segs&, int, int, hipStream_t); \
+    template hipError_t launch_inject<real, DIM>(const Geom&, const PArrays<real>&, const Segs&,               \
+                                                 const PArrays<real>&, int32_t*, const InjectArgs&, hipStream_t);
+SPINPIC_WINDOW_INST(float, 2)
+SPINPIC_WINDOW_INST(float, 3)
+SPINPIC_WINDOW_INST(double, 2)
+SPINPIC_WINDOW_INST(double, 3)
+#undef SPINPIC_WINDOW_INST
 
 template hipError_t launch_push_tiles_batch<float, double>(const RunDesc<float>*, const TileRef*, int, int,
     size_t, const PArrays<float>&, const Segs&, const PArrays<float>&, int32_t*, int, const Fields<freal>&, int,

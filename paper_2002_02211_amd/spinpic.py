@@ -27,7 +27,7 @@ MAX_SPECIES = 4
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
             "pic_spectrum", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
-            "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
+            "pic_window", "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
             "pic_batch_init", "pic_batch_step", "pic_batch_polarization", "pic_batch_fields",
             "pic_batch_particles", "pic_batch_info", "pic_batch_tuning", "pic_batch_stats",
             "pic_batch_timing", "pic_batch_timing_read", "pic_batch_last_error", "pic_batch_free",
@@ -75,6 +75,12 @@ class TrackConfig(ctypes.Structure):
                 ("precision", ctypes.c_int32)]
 
 
+class WindowConfig(ctypes.Structure):
+    _fields_ = [("speed", ctypes.c_double), ("shift_cells", ctypes.c_int32), ("ppc", ctypes.c_int32),
+                ("n0", ctypes.c_double), ("ramp_start", ctypes.c_double), ("ramp_len", ctypes.c_double),
+                ("s0", ctypes.c_double * 3)]
+
+
 class Allocator(ctypes.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
 
@@ -113,6 +119,7 @@ def load_library(path=LIB_PATH):
     lib.pic_density.argtypes = [P, ctypes.c_int32, D, ctypes.c_size_t]
     lib.pic_energy.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
     lib.pic_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.pic_window.argtypes = [P, ctypes.POINTER(WindowConfig)]
     lib.pic_timing.argtypes = [P, ctypes.c_int32]
     lib.pic_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
@@ -330,10 +337,28 @@ def pic_energy(ctx, nspecies):
 
 
 def pic_stats(ctx):
-    out = (ctypes.c_int64 * 8)()
-    _check(load_library().pic_stats(ctx, out, 8), ctx)
+    out = (ctypes.c_int64 * 13)()
+    _check(load_library().pic_stats(ctx, out, 13), ctx)
     return {"steps": out[0], "moved": out[1], "overflow": out[2], "repacks": out[3],
-            "particles": out[4], "tile": (out[5], out[6], out[7])}
+            "particles": out[4], "tile": (out[5], out[6], out[7]),
+            "per_species": [out[8], out[9], out[10], out[11]], "shifts": out[12]}
+
+
+def window_config(speed=1.0, shift_cells=16, ppc=0, n0=0.0, ramp_start=0.0, ramp_len=0.0, s0=(0.0, 1.0, 0.0)):
+    w = WindowConfig()
+    w.speed = float(speed)
+    w.shift_cells = int(shift_cells)
+    w.ppc = int(ppc)
+    w.n0 = float(n0)
+    w.ramp_start = float(ramp_start)
+    w.ramp_len = float(ramp_len)
+    for i in range(3):
+        w.s0[i] = float(s0[i])
+    return w
+
+
+def pic_window(ctx, w):
+    _check(load_library().pic_window(ctx, ctypes.byref(w)), ctx)
 
 
 def pic_timing(ctx, enable):
@@ -383,7 +408,13 @@ class Simulation:
         return {nm: arr[i] for i, nm in enumerate(order)}
 
     def particles(self, species):
-        return pic_particles(self.ctx, species, self.counts[species])
+        """Rows (id, x y z, u, s, w) of the particles in the box, sorted by id."""
+        count = self.stats()["per_species"][species]
+        return pic_particles(self.ctx, species, count)
+
+    def window(self, **kw):
+        """Open the x faces and start a moving window (see window_config)."""
+        pic_window(self.ctx, window_config(**kw))
 
     def energy(self):
         return pic_energy(self.ctx, self.nspecies)

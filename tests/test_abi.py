@@ -36,6 +36,8 @@ def test_exports_every_declared_function(lib):
     # ctypes mirrors of the structs: the C side reads fields out to the last one
     assert ctypes.sizeof(S.Config) == 4 + 12 + 24 + 8 + 4 + 4 + 4 * 24 + 12 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(S.State) == 8 * 4 + 8 * 4 + 8
+    assert ctypes.sizeof(S.WindowConfig) == 8 + 4 + 4 + 3 * 8 + 3 * 8
+    assert S.WindowConfig.s0.offset == 40 and S.WindowConfig.n0.offset == 16
 
 
 def _good_cfg(**kw):
@@ -157,6 +159,7 @@ def test_T16_calls_on_null_context(lib):
     assert lib.pic_spectrum(None, 0, 0.0, 1.0, 4, None, None, None) == S.PIC_ESTATE
     assert lib.pic_phase_space(None, 0, 0, 0.0, 1.0, 4, 0, -1.0, 1.0, 4, None) == S.PIC_ESTATE
     assert lib.pic_density(None, 0, None, 0) == S.PIC_ESTATE
+    assert lib.pic_window(None, ctypes.byref(S.window_config())) == S.PIC_ESTATE
     lib.pic_free(None)
 
 
