@@ -322,9 +322,12 @@ def bench_batch(args):
     ncells = sum(int(s["n"][0]) * int(s["n"][1]) for s in specs)
     print("[bench] c5: %d runs, %d particles, %d cells generated in %.1f s"
           % (len(specs), npart, ncells, time.time() - t0), file=sys.stderr, flush=True)
-    cfgs = [S.config_from_spec(s, precision="fp32") for s in specs]
+    # --tile: every run at that tile, no autotuning (for counter runs that
+    # must see only the timed steps' push launches)
+    tile = tuple(int(v) for v in args.tile.split(",")) + (1,) if args.tile else (0, 0, 1)
+    cfgs = [S.config_from_spec(s, precision="fp32", tile=tile[:3]) for s in specs]
 
-    b, t_init, elapsed, timers = _time_batch(S, cfgs, pairs, True, args.warmup, args.steps)
+    b, t_init, elapsed, timers = _time_batch(S, cfgs, pairs, not args.tile, args.warmup, args.steps)
     stats = b.stats()
     tiles = [b.info(r)["tile"] for r in range(len(specs))]
     tu = b.tuning()
@@ -362,10 +365,11 @@ def bench_batch(args):
                      "bytes_per_cell": per_cell, "avg_launch_ms": avg_push_s * 1e3,
                      "push_pushes_per_s": npart / avg_push_s},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
-        "autotune": {"init_s": t_init, "candidates": tu["candidates"],
-                     "push_ms_uniform": np.round(tu["kernel_ms"], 4).tolist(),
-                     "push_ms_per_run_tiles": round(tu["mixed_ms"], 4),
-                     "share_ns_per_particle_step_median": np.median(tu["share_ns"], axis=0).round(4).tolist()},
+        "autotune": ({"init_s": t_init, "candidates": tu["candidates"],
+                      "push_ms_uniform": np.round(tu["kernel_ms"], 4).tolist(),
+                      "push_ms_per_run_tiles": round(tu["mixed_ms"], 4),
+                      "share_ns_per_particle_step_median": np.median(tu["share_ns"], axis=0).round(4).tolist()}
+                     if tu else None),
         "polarization_run0": pol[0],
     }
     result.update(result_extra)
