@@ -1440,6 +1440,7 @@ private:
     double* acc_ = nullptr;
     RunDesc<real>* d_runs_ = nullptr;
     TileRef* d_order_ = nullptr;
+    XcdQueues xq_{};
     int32_t* d_blk_run_ = nullptr;   // field-update block -> run
     int fdtd_nblk_ = 0;
     std::vector<TileRef> order_;
@@ -1754,22 +1755,35 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     for (int b = 0; b < 2; ++b)
         for (int a = 0; a < 3; ++a) HIP_OR_FAIL(hipMemsetAsync(jbuf_[b][a], 0, ncells_ * sizeof(freal), stream_));
 
-    // ---- tiles largest first, run descriptors, persistent grid size
-    std::vector<std::pair<long long, TileRef>> cost(ntiles_);
-    for (int r = 0; r < nrun; ++r) {
-        const Run& R = runs_[r];
-        for (int t = 0; t < R.g.ntiles; ++t) {
-            long long c = 0;
-            for (int s = 0; s < nsp_; ++s) c += count[R.sid_base + t * nsp_ + s];
-            cost[R.tile_base + t] = {c, TileRef{r, t}};
-        }
-    }
-    std::stable_sort(cost.begin(), cost.end(),
-                     [](const std::pair<long long, TileRef>& a, const std::pair<long long, TileRef>& b) {
-                         return a.first > b.first;
-                     });
+    // ---- work list: each run's tiles in row-major order, cut into 8
+    // contiguous chunks of about equal cost (particles + cells), one per XCD
     order_.resize(ntiles_);
-    for (int i = 0; i < ntiles_; ++i) order_[i] = cost[i].second;
+    {
+        std::vector<double> cost(ntiles_);
+        double total = 0.0;
+        for (int r = 0; r < nrun; ++r) {
+            const Run& R = runs_[r];
+            for (int t = 0; t < R.g.ntiles; ++t) {
+                long long c = 0;
+                for (int s = 0; s < nsp_; ++s) c += count[R.sid_base + t * nsp_ + s];
+                const int tx = t % R.g.nt[0], ty = t / R.g.nt[0];
+                const long long cells = (long long)std::min(R.g.T[0], R.g.n[0] - tx * R.g.T[0]) *
+                                        std::min(R.g.T[1], R.g.n[1] - ty * R.g.T[1]);
+                order_[R.tile_base + t] = TileRef{r, t};
+                cost[R.tile_base + t] = (double)(c + cells);
+                total += (double)(c + cells);
+            }
+        }
+        xq_.start[0] = 0;
+        double acc = 0.0;
+        int x = 1;
+        for (int i = 0; i < ntiles_ && x < 8; ++i) {
+            acc += cost[i];
+            while (x < 8 && acc >= total * x / 8.0) xq_.start[x++] = i + 1;
+        }
+        while (x < 8) xq_.start[x++] = ntiles_;
+        xq_.start[8] = ntiles_;
+    }
     HIP_OR_FAIL(hipMemcpyAsync(d_order_, order_.data(), ntiles_ * sizeof(TileRef), hipMemcpyHostToDevice, stream_));
     {
         std::vector<int32_t> blk_run((size_t)fdtd_nblk_);
@@ -1789,7 +1803,8 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int per_cu = use_acc64_ ? push_batch_blocks_per_cu<real, double>(push_lds())
                                   : push_batch_blocks_per_cu<real, real>(push_lds());
-    push_blocks_ = std::max(1, std::min(ntiles_, cus * per_cu));
+    // a multiple of 8, so that every XCD runs the same number of workgroups
+    push_blocks_ = std::max(8, std::min(ntiles_, cus * per_cu) / 8 * 8);
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
     return Status{};
 }
@@ -1811,10 +1826,10 @@ Status BatchEngine<real>::step(int nsteps) {
         unsigned long long* rn = time_runs_ ? run_ns_ : nullptr;
         timer_start(timer_, stream_, 0);
         if (use_acc64_)
-            HIP_OR_FAIL((launch_push_tiles_batch<real, double>(d_runs_, d_order_, ntiles_, push_blocks_, lds, p_, seg_,
+            HIP_OR_FAIL((launch_push_tiles_batch<real, double>(d_runs_, d_order_, xq_, push_blocks_, lds, p_, seg_,
                                                                lv_, ctr_, slot, f_, deposit_, rn, stream_)));
         else
-            HIP_OR_FAIL((launch_push_tiles_batch<real, real>(d_runs_, d_order_, ntiles_, push_blocks_, lds, p_, seg_,
+            HIP_OR_FAIL((launch_push_tiles_batch<real, real>(d_runs_, d_order_, xq_, push_blocks_, lds, p_, seg_,
                                                              lv_, ctr_, slot, f_, deposit_, rn, stream_)));
         timer_stop(timer_, stream_, 0);
         timer_start(timer_, stream_, 1);

@@ -87,9 +87,9 @@ enum {
     CTR_LEAVE0 = 0,   // leavers of even steps
     CTR_LEAVE1 = 1,   // leavers of odd steps
     CTR_STASH = 2,    // particles in the overflow store
-    CTR_QUEUE0 = 4,   // next work item of the batched push, even steps
-    CTR_QUEUE1 = 5,   // odd steps
-    CTR_NCTR = 8
+    CTR_QUEUE = 8,    // next work item of the batched push: 8 per XCD queue,
+                      // even steps at CTR_QUEUE, odd steps at CTR_QUEUE + 8
+    CTR_NCTR = 24
 };
 
 // ---------------------------------------------------------------- cells

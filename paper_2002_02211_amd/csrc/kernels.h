@@ -50,10 +50,17 @@ struct TileRef {
     int t;   // tile index within the run
 };
 
-// Persistent push: blocks workgroups take tiles from order[0 .. ntiles) in
-// turn; run_ns (nruns counters, may be NULL) accumulates each run's tile time.
+// The batched push's queues: the work list cut into 8 contiguous chunks,
+// one per XCD (chunk x = items [start[x], start[x + 1])).
+struct XcdQueues {
+    int start[9];
+};
+
+// Persistent push: blocks workgroups (a multiple of 8) take tiles from the
+// queue of their XCD, then from the others; run_ns (nruns counters, may be
+// NULL) accumulates each run's tile time.
 template <typename real, typename acc_t>
-hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, int ntiles, int blocks,
+hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, const XcdQueues& q, int blocks,
                                    size_t lds, const PArrays<real>& p, const Segs& seg, const PArrays<real>& lv,
                                    int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
                                    unsigned long long* run_ns, hipStream_t stream);

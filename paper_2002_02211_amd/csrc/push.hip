@@ -565,25 +565,44 @@ __device__ inline Fields<freal> run_fields(const Fields<freal>& f, long long off
     return r;
 }
 
-// Persistent push over the tiles of every run, largest tiles first: each
-// workgroup takes the next tile from a counter until none is left.  The
-// counter of the other step parity is cleared for the next step.
+// Persistent push over the tiles of every run.  The work list holds each
+// run's tiles in row-major order, cut into 8 contiguous chunks of about
+// equal cost, one per XCD: workgroup b runs on XCD b mod 8 (workgroups are
+// dealt round-robin over the XCDs) and takes the next tile of its XCD's
+// chunk from a counter, so neighbouring tiles, which share guard cells,
+// are worked on by one L2; when its chunk is used up it takes tiles from
+// the other chunks in turn.  The other step parity's counters are cleared
+// for the next step.
 template <typename real, typename acc_t>
 __global__ void __launch_bounds__(kBlock)
-k_push_tiles_batch(const RunDesc<real>* __restrict__ runs, const TileRef* __restrict__ order, int ntiles,
+k_push_tiles_batch(const RunDesc<real>* __restrict__ runs, const TileRef* __restrict__ order, XcdQueues q,
                    PArrays<real> p, Segs seg, PArrays<real> lv, int32_t* __restrict__ ctr, int slot,
                    Fields<freal> f, int deposit, unsigned long long* __restrict__ run_ns) {
     __shared__ int s_item;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr[slot ^ 1] = 0;
-        ctr[CTR_QUEUE0 + (slot ^ 1)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+        if (threadIdx.x == 0) ctr[slot ^ 1] = 0;
+        ctr[CTR_QUEUE + 8 * (slot ^ 1) + threadIdx.x] = 0;
     }
+    int32_t* const queue = ctr + CTR_QUEUE + 8 * slot;
+    int x = blockIdx.x & 7, tried = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&ctr[CTR_QUEUE0 + slot], 1);
+        if (threadIdx.x == 0) {
+            int item = -1;
+            while (tried < 8) {
+                const int k = atomicAdd(&queue[x], 1);
+                if (k < q.start[x + 1] - q.start[x]) {
+                    item = q.start[x] + k;
+                    break;
+                }
+                ++tried;
+                x = (x + 1) & 7;
+            }
+            s_item = item;
+        }
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (item >= ntiles) break;
+        if (item < 0) break;
         const TileRef tr = order[item];
         const Geom g = runs[tr.run].g;
         const Consts<real> k = runs[tr.run].k;
@@ -775,12 +794,12 @@ hipError_t launch_insert(const Geom& g, const PArrays<real>& p, const Segs& seg,
 }
 
 template <typename real, typename acc_t>
-hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, int ntiles, int blocks,
+hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* order, const XcdQueues& q, int blocks,
                                    size_t lds, const PArrays<real>& p, const Segs& seg, const PArrays<real>& lv,
                                    int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
                                    unsigned long long* run_ns, hipStream_t stream) {
     hipLaunchKernelGGL((k_push_tiles_batch<real, acc_t>), dim3(blocks), dim3(kBlock), lds, stream, runs, order,
-                       ntiles, p, seg, lv, ctr, slot, f, deposit, run_ns);
+                       q, p, seg, lv, ctr, slot, f, deposit, run_ns);
     return hipGetLastError();
 }
 
@@ -811,13 +830,13 @@ SPINPIC_WINDOW_INST(double, 2)
 SPINPIC_WINDOW_INST(double, 3)
 #undef SPINPIC_WINDOW_INST
 
-template hipError_t launch_push_tiles_batch<float, double>(const RunDesc<float>*, const TileRef*, int, int,
+template hipError_t launch_push_tiles_batch<float, double>(const RunDesc<float>*, const TileRef*, const XcdQueues&, int,
     size_t, const PArrays<float>&, const Segs&, const PArrays<float>&, int32_t*, int, const Fields<freal>&, int,
     unsigned long long*, hipStream_t);
-template hipError_t launch_push_tiles_batch<float, float>(const RunDesc<float>*, const TileRef*, int, int,
+template hipError_t launch_push_tiles_batch<float, float>(const RunDesc<float>*, const TileRef*, const XcdQueues&, int,
     size_t, const PArrays<float>&, const Segs&, const PArrays<float>&, int32_t*, int, const Fields<freal>&, int,
     unsigned long long*, hipStream_t);
-template hipError_t launch_push_tiles_batch<double, double>(const RunDesc<double>*, const TileRef*, int, int,
+template hipError_t launch_push_tiles_batch<double, double>(const RunDesc<double>*, const TileRef*, const XcdQueues&, int,
     size_t, const PArrays<double>&, const Segs&, const PArrays<double>&, int32_t*, int, const Fields<freal>&,
     int, unsigned long long*, hipStream_t);
 template hipError_t launch_push_stash_batch<float>(const RunDesc<float>*, const PArrays<float>&, const int32_t*,
