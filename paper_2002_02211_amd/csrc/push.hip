@@ -347,6 +347,20 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                 return lprefix[c] + __popcll(leavemask[c] & ((1ull << (x & 63)) - 1ull));
             };
             const int pairs = leavers_below(nn);
+            // slot of the leaver of rank q (0 <= q < L): the last chunk whose
+            // exclusive prefix count is at most q, then the (q - prefix)-th
+            // set bit of its ballot
+            auto leaver_slot = [&](int q) {
+                int lo = 0, hi = nchunks - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (lprefix[mid] <= q) lo = mid;
+                    else hi = mid - 1;
+                }
+                unsigned long long m = leavemask[lo];
+                for (int k = q - lprefix[lo]; k > 0; --k) m &= m - 1ull;
+                return (lo << 6) + __builtin_ctzll(m);
+            };
             for (int r0 = 0; r0 == 0 || r0 < pairs; r0 += kPairCap) {
                 for (int q = threadIdx.x; q < L; q += kBlock) {
                     const int pos = nn + q;
@@ -356,19 +370,21 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                     }
                 }
                 __syncthreads();
-                for (int ch = wave; ch < nchunks; ch += kBlock / 64) {
-                    const unsigned long long m = leavemask[ch];
-                    if ((m >> lane) & 1ull) {
-                        const int h = (ch << 6) + lane;
-                        const int rank = lprefix[ch] + __popcll(m & ((1ull << lane) - 1ull));
-                        // the leaver is read before its slot is refilled (same thread)
-                        if (r0 == 0) {
-                            copy_particle(p, (long long)start + h, lv, (long long)lbase + rank, DIM);
-                            lv.sp[lbase + rank] = inst_tag + sp;
-                        }
-                        if (h < nn && rank >= r0 && rank < r0 + kPairCap)
-                            copy_particle(p, (long long)start + srcpos[rank - r0], p, (long long)start + h, DIM);
+                // one thread per leaver: its copy to the leaver store and, if
+                // its slot lies below the new end n - L (rank < pairs), the
+                // copy of the tail particle that fills it; all leavers of
+                // the segment are handled at once instead of chunk by chunk
+                for (int q = threadIdx.x; q < L; q += kBlock) {
+                    const bool out = r0 == 0;
+                    const bool fill = q >= r0 && q < pairs && q < r0 + kPairCap;
+                    if (!out && !fill) continue;
+                    const int h = leaver_slot(q);
+                    // the leaver is read before its slot is refilled (same thread)
+                    if (out) {
+                        copy_particle(p, (long long)start + h, lv, (long long)lbase + q, DIM);
+                        lv.sp[lbase + q] = inst_tag + sp;
                     }
+                    if (fill) copy_particle(p, (long long)start + srcpos[q - r0], p, (long long)start + h, DIM);
                 }
                 __syncthreads();
             }
