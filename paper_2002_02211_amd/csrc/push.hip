@@ -107,7 +107,7 @@ __device__ inline void copy_particle(const PArrays<real>& from, long long i, con
 // leavers carry inst_tag + sp in the leaver store's species word.  Every
 // thread of the workgroup must call it.
 template <typename real, typename acc_t, int DIM>
-__device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
+__device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
                           const PArrays<real>& lv, int32_t* __restrict__ ctr, int slot, const Fields<freal>& f,
                           int deposit, int t, int sid_base, int inst_tag) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -137,6 +137,28 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
     int* lprefix = reinterpret_cast<int*>(smem + lm_off + align16((size_t)(seg.max_chunks + 4) * 8));
     int* srcpos = reinterpret_cast<int*>(smem + lm_off + align16((size_t)(seg.max_chunks + 4) * 8) +
                                          align16((size_t)(seg.max_chunks + 4) * 4));
+
+    // Software pipeline: the next particle of this thread is loaded while
+    // the current one is pushed.  Every lane issues the same loads and
+    // stores in every iteration (clamped load index, masked-off lanes
+    // storing into the spare slots), so the wait for the prefetched data
+    // does not also wait for this iteration's stores to complete.
+    int cell_n = 0;
+    real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
+         s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
+    auto load = [&](int start, int i) {
+        const uint32_t bi = (uint32_t)(start + i) * 4u;
+        const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
+        cell_n = ldo(p.cell, bi);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) o_n[a] = ldo(p.off[a], br);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u_n[a] = ldo(p.u[a], br);
+            s_n[a] = ldo(p.s[a], br);
+        }
+        w_n = ldo(p.w, br);
+    };
 
     // stage E and B: each thread owns one x position of several (y, z) rows
     // and issues the loads of up to kStageRows rows before writing any
@@ -195,29 +217,7 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
         const int start = __builtin_amdgcn_readfirstlane(seg.start[sid]);
         const int n = __builtin_amdgcn_readfirstlane(seg.count[sid]);
         const real eps = k.eps[sp], r = k.r[sp], an = k.a[sp], Z = k.Z[sp];
-
-        // Software pipeline: the next particle of this thread is loaded while
-        // the current one is pushed.  Every lane issues the same loads and
-        // stores in every iteration (clamped load index, masked-off lanes
-        // storing into the spare slots), so the wait for the prefetched data
-        // does not also wait for this iteration's stores to complete.
-        int cell_n = 0;
-        real o_n[3] = {real(0), real(0), real(0)}, u_n[3] = {real(0), real(0), real(0)},
-             s_n[3] = {real(0), real(0), real(0)}, w_n = real(0);
-        auto load = [&](int i) {
-            const uint32_t bi = (uint32_t)(start + i) * 4u;
-            const uint32_t br = (uint32_t)(start + i) * (uint32_t)sizeof(real);
-            cell_n = ldo(p.cell, bi);
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) o_n[a] = ldo(p.off[a], br);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                u_n[a] = ldo(p.u[a], br);
-                s_n[a] = ldo(p.s[a], br);
-            }
-            w_n = ldo(p.w, br);
-        };
-        if (n > 0) load(min((int)threadIdx.x, n - 1));
+        if (n > 0) load(start, min((int)threadIdx.x, n - 1));
 
         for (int base = 0; base < n; base += kBlock) {
             const int i = base + threadIdx.x;
@@ -231,7 +231,7 @@ __device__ void push_tile(const Geom& g, const Consts<real>& k, const PArrays<re
                 s[a] = s_n[a];
             }
             const real wgt = w_n;
-            if (base + kBlock < n) load(min(i + kBlock, n - 1));
+            if (base + kBlock < n) load(start, min(i + kBlock, n - 1));
 
             bool leave = false;
             int newcell = cell0;
@@ -620,11 +620,12 @@ k_push_tiles_batch(const RunDesc<real>* __restrict__ runs, const TileRef* __rest
         __syncthreads();
         if (item < 0) break;
         const TileRef tr = order[item];
-        const Geom g = runs[tr.run].g;
-        const Consts<real> k = runs[tr.run].k;
-        const Fields<freal> fr = run_fields<real>(f, runs[tr.run].cell_off);
+        // the run's geometry and constants are read in place: a local copy
+        // of the constants, indexed by species, would live in scratch memory
+        const RunDesc<real>& rd = runs[tr.run];
+        const Fields<freal> fr = run_fields<real>(f, rd.cell_off);
         const unsigned long long t0 = run_ns ? wall_clock64() : 0ull;
-        push_tile<real, acc_t, 2>(g, k, p, seg, lv, ctr, slot, fr, deposit, tr.t, runs[tr.run].sid_base,
+        push_tile<real, acc_t, 2>(rd.g, rd.k, p, seg, lv, ctr, slot, fr, deposit, tr.t, rd.sid_base,
                                   tr.run * kMaxSpecies);
         __syncthreads();   // shared memory is restaged for the next tile
         if (run_ns && threadIdx.x == 0) atomicAdd(run_ns + tr.run, (wall_clock64() - t0) * 10ull);
