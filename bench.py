@@ -517,6 +517,7 @@ def main():
               "(domain decomposition over several GPUs is design-only)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import synth
     from paper_2002_02211_amd import spinpic as S
@@ -619,7 +620,8 @@ def main():
             "value": npart * args.steps / el64, "unit": "pushes/s",
             "ms_per_step": el64 / args.steps * 1e3,
             "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
-            "dP_max_fp32_vs_fp64": float(max(abs(a - b) for a, b in zip(P, P64))),
+            "dP_max_fp32_vs_fp64": float(np.max(np.abs(np.asarray(P) - np.asarray(P64)))),
+            "P_fp32": [float(v) for v in P], "P_fp64": [float(v) for v in P64],
             "after_steps": args.warmup + args.steps}
 
     if not args.no_cpu_baseline:
