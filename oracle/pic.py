@@ -516,6 +516,7 @@ class Sim:
         self.J = np.zeros((3,) + g.shape)
         self.mur = MurState(self.E, self.B, g) if g.open_x else None
         self.nstep = 0
+        self.window_step0 = 0
         self.residual0 = div_E(self.E, g) - self.rho()
 
     def rho(self):
@@ -593,12 +594,24 @@ class Sim:
             return w["n0"] * np.clip((x - w["ramp_start"]) / w["ramp_len"], 0.0, 1.0)
         return np.where(x >= w["ramp_start"], w["n0"], 0.0)
 
+    def enable_window(self, window):
+        """Open the x faces and start a window now (the travel and the lab
+        frame count from this step); the div E - rho reference is taken again
+        with the open faces."""
+        self.window = dict(window)
+        self.grid.open_x = True
+        self.mur = MurState(self.E, self.B, self.grid)
+        self.window_step0 = self.nstep
+        self.shifts = 0
+        self.residual0 = div_E(self.E, self.grid) - self.rho()
+
     def _advance_window(self):
-        """After step n the window has moved n speed dt; every whole
-        shift_cells cells of that it shifts the box by shift_cells cells."""
+        """After step n (counted from the window's start) the window has
+        moved n speed dt; every whole shift_cells cells of that it shifts the
+        box by shift_cells cells."""
         w, g = self.window, self.grid
         S = int(w["shift_cells"])
-        while self.nstep * w["speed"] * g.dt >= (self.shifts + 1) * S * g.d[0]:
+        while (self.nstep - self.window_step0) * w["speed"] * g.dt >= (self.shifts + 1) * S * g.d[0]:
             self._shift(S)
 
     def _shift(self, S):

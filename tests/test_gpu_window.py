@@ -48,6 +48,8 @@ CASES = [
      _win(shift_cells=8, ppc=3, n0=0.05, ramp_start=26.0, ramp_len=6.0, s0=(0.0, 0.0, 1.0)), (20, 50)),
     ("2d-open-box", "small2d", (16, 16, 1), _win(speed=0.0, shift_cells=16), (20, 30, 40, 50, 60)),
     ("3d", "small3d", (0, 0, 0), _win(shift_cells=6, ppc=1, n0=0.05, s0=(1.0, 0.0, 0.0)), (12, 25)),
+    ("2d-two-columns", "small2d", (8, 8, 1),
+     _win(shift_cells=16, ppc=1, n0=0.04, ramp_start=24.0, ramp_len=3.0), (30, 50)),
 ]
 
 
@@ -99,6 +101,25 @@ def test_window_fp64_matches_oracle(name, preset, tile, win, checks):
     assert ref.shifts >= (2 if win["speed"] > 0 else 0)
     if win["speed"] == 0.0:
         assert sum(x.shape[0] for x in ref.xi) < sum(p.shape[0] for p in state["particles"])
+    sim.close()
+
+
+def test_window_opened_after_periodic_steps():
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    win = _win(shift_cells=16, ppc=2, n0=0.03)
+    _say("window fp64 opened after 8 periodic steps")
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp64"), state["particles"], state["fields"])
+    ref = oracle.Sim(spec, state)
+    sim.step(8)
+    ref.step(8)
+    sim.window(**win)
+    ref.enable_window(win)
+    sim.step(42)
+    ref.step(42)
+    worst, st = _compare(sim, ref, spec, 1e-9, "late window")
+    _say("late window shifts", st["shifts"], "worst particle error %.2e" % worst)
+    assert ref.shifts >= 1
     sim.close()
 
 

@@ -78,6 +78,7 @@ WINDOW = [
     TW.test_shift_moves_fields_and_clears_new_columns,
     TW.test_gather_sees_nothing_beyond_the_faces,
     TW.test_no_current_crosses_a_face,
+    TW.test_window_started_later_counts_travel_from_its_start,
 ]
 
 MUTANTS = [
@@ -137,6 +138,7 @@ MUTANTS = [
     ("Sim._inject", "self.next_id[k] += nz * ny * S * ppc", "self.next_id[k] += m", WINDOW),
     ("Sim.window_density", '(x - w["ramp_start"]) / w["ramp_len"]', '(x - w["ramp_start"]) * w["ramp_len"]', WINDOW),
     ("Sim._advance_window", ">= (self.shifts + 1) * S", ">= (self.shifts + 2) * S", WINDOW),
+    ("Sim._advance_window", "(self.nstep - self.window_step0)", "self.nstep", WINDOW),
 ]
 
 

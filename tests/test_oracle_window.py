@@ -320,3 +320,20 @@ def test_no_current_crosses_a_face():
     assert sim.xi[0][0, 0] >= nx
     assert np.any(sim.J[..., nx - 2:])
     assert not np.any(sim.J[..., :nx - 3])
+
+
+def test_window_started_later_counts_travel_from_its_start():
+    """A window opened after some periodic steps shifts as one opened at the
+    start of a run that begins there."""
+    nx, ny, S = 48, 6, 4
+    spec = _vac_spec(nx, ny, nsp=2)
+    st = _lattice_state(spec, 2, 0.01)
+    a = Sim(spec, st)
+    a.step(7)
+    a.enable_window(_window(S=S, ppc=2, n0=0.01))
+    a.step(30)
+    b = Sim(spec, st, window=_window(S=S, ppc=2, n0=0.01))
+    b.step(30)
+    assert a.shifts == b.shifts == int(30 * a.grid.dt / (S * D))
+    for k in range(2):
+        np.testing.assert_array_equal(a.particles(k), b.particles(k))
