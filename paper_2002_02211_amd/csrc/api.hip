@@ -262,6 +262,7 @@ public:
 private:
     Status window_shift();
     Status live_counts(long long out[kMaxSpecies]);
+    Status stored_count(long long* n);
     Status grow_stores(long long need);
     // device memory
     void* dalloc(size_t bytes) {
@@ -341,6 +342,8 @@ private:
     long long shifts_ = 0;
     long long next_id_[kMaxSpecies] = {0, 0, 0, 0};
     freal* scratch_ = nullptr;     // one field array, for the shifts
+    Segs seg_tmp_{};               // a second segment table, for the shifts
+    long long npart_bound_ = 0;    // stored entries at the last count + injected since
     Timer timer_;
 };
 
@@ -1177,6 +1180,22 @@ Status Engine<real, DIM>::live_counts(long long out[kMaxSpecies]) {
     return Status{};
 }
 
+// Entries of the segments and of the overflow store, dead overflow entries
+// included.  Until the next repack the overflow store can gain at most one
+// entry per particle now in a segment and per particle injected later, so
+// this number plus the later injections bounds the size of both stores.
+template <typename real, int DIM>
+Status Engine<real, DIM>::stored_count(long long* n) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    std::vector<int32_t> cnt(nseg_);
+    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int32_t nst = 0;
+    HIP_OR_FAIL(hipMemcpy(&nst, ctr_ + CTR_STASH, sizeof nst, hipMemcpyDeviceToHost));
+    *n = nst;
+    for (int sg = 0; sg < nseg_; ++sg) *n += cnt[sg];
+    return Status{};
+}
+
 // The leaver and overflow stores must hold every particle of the box (all
 // may leave their tile in one step); injection can raise that number.  Both
 // are empty between steps, so they are replaced without copying.
@@ -1217,7 +1236,15 @@ Status Engine<real, DIM>::window(const pic_window_config* w) {
     if (!scratch_) {
         scratch_ = (freal*)dalloc(g_.ncells * sizeof(freal));
         f_.mur = (freal*)dalloc((size_t)MUR_COLUMNS * g_.n[1] * g_.n[2] * sizeof(freal));
-        if (!scratch_ || !f_.mur) return fail(PIC_ENOMEM, "device allocation failed");
+        seg_tmp_.start = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
+        seg_tmp_.cap = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
+        seg_tmp_.count = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
+        if (!scratch_ || !f_.mur || !seg_tmp_.start || !seg_tmp_.cap || !seg_tmp_.count)
+            return fail(PIC_ENOMEM, "device allocation failed");
+    }
+    {
+        Status L = stored_count(&npart_bound_);
+        if (L.code) return L;
     }
     win_ = *w;
     win_on_ = true;
@@ -1236,17 +1263,35 @@ Status Engine<real, DIM>::window(const pic_window_config* w) {
 }
 
 // One shift of the moving window by S = shift_cells cells (a whole number k
-// of tile columns): the overflow store is folded back first, every field
-// array moves S cells towards -x, the segment table rotates by k tile
-// columns (the first k columns' segments, whose particles leave the box,
-// become the last k columns' with count 0), the kept particles move S cells
-// down in x, and cold plasma is injected into the last S columns.
+// of tile columns): every field array moves S cells towards -x, the segment
+// table rotates by k tile columns (the first k columns' segments, whose
+// particles leave the box, become the last k columns' with count 0), the
+// kept particles and the overflow store's move S cells down in x, and cold
+// plasma is injected into the last S columns.  All of it is queued on the
+// stream without a wait, unless the particle stores have to grow.
 template <typename real, int DIM>
 Status Engine<real, DIM>::window_shift() {
     const int S = win_.shift_cells;
     const int k = S / g_.T[0];
-    Status St = repack();   // waits; empties the overflow store
-    if (St.code) return St;
+    const int nz = DIM == 3 ? g_.n[2] : 1;
+    const long long per_sp = (long long)nz * g_.n[1] * S * win_.ppc;
+    // The leaver and overflow stores must not run out: npart_bound_ (the
+    // stored entries at the last count plus the particles injected since)
+    // bounds what they can receive.  It counts no removals; it is recounted
+    // (a wait and a read of the counts) only when the stores would otherwise
+    // have to grow, and growing them needs an empty overflow store.
+    if (win_.ppc > 0 && npart_bound_ + per_sp * g_.nsp > store_cap_) {
+        Status St = stored_count(&npart_bound_);
+        if (St.code) return St;
+        if (npart_bound_ + per_sp * g_.nsp > store_cap_) {
+            St = repack();
+            if (St.code) return St;
+            St = stored_count(&npart_bound_);
+            if (St.code) return St;
+            St = grow_stores(npart_bound_ + per_sp * g_.nsp);
+            if (St.code) return St;
+        }
+    }
     // fields and the last step's current
     freal** arrs[9] = {&f_.E[0], &f_.E[1], &f_.E[2], &f_.B[0], &f_.B[1], &f_.B[2],
                        &jbuf_[jcur_][0], &jbuf_[jcur_][1], &jbuf_[jcur_][2]};
@@ -1257,36 +1302,15 @@ Status Engine<real, DIM>::window_shift() {
     for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
     HIP_OR_FAIL((launch_mur_reset<freal, DIM>(g_, f_, stream_)));
     // segment table
-    std::vector<int32_t> start(nseg_), cap(nseg_), cnt(nseg_);
-    HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_OR_FAIL(hipMemcpy(cap.data(), seg_.cap, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_OR_FAIL(hipMemcpy(cnt.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> nstart(nseg_), ncap(nseg_), ncnt(nseg_);
-    const int ntx = g_.nt[0];
-    for (int t = 0; t < g_.ntiles; ++t) {
-        const int tx = t % ntx;
-        const bool kept = tx < ntx - k;
-        const int src_t = t - tx + (kept ? tx + k : tx - (ntx - k));
-        for (int sp = 0; sp < g_.nsp; ++sp) {
-            const int d = t * g_.nsp + sp, s = src_t * g_.nsp + sp;
-            nstart[d] = start[s];
-            ncap[d] = cap[s];
-            ncnt[d] = kept ? cnt[s] : 0;
-        }
-    }
-    HIP_OR_FAIL(hipMemcpyAsync(seg_.start, nstart.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
-    HIP_OR_FAIL(hipMemcpyAsync(seg_.cap, ncap.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
-    HIP_OR_FAIL(hipMemcpyAsync(seg_.count, ncnt.data(), nseg_ * sizeof(int32_t), hipMemcpyHostToDevice, stream_));
+    HIP_OR_FAIL(launch_rotate_segments(g_, seg_, seg_tmp_, k, stream_));
+    std::swap(seg_.start, seg_tmp_.start);
+    std::swap(seg_.cap, seg_tmp_.cap);
+    std::swap(seg_.count, seg_tmp_.count);
     HIP_OR_FAIL((launch_shift_cells<real, DIM>(p_, seg_, S, nseg_, stream_)));
-    // injection
-    long long live = 0;
-    for (int d = 0; d < nseg_; ++d) live += ncnt[d];
-    const int nz = DIM == 3 ? g_.n[2] : 1;
-    const long long per_sp = (long long)nz * g_.n[1] * S * win_.ppc;
+    HIP_OR_FAIL((launch_shift_stash<real, DIM>(st_, ctr_, S, stream_)));
     shifts_++;
     if (win_.ppc > 0) {
-        St = grow_stores(live + per_sp * g_.nsp);
-        if (St.code) return St;
+        npart_bound_ += per_sp * g_.nsp;
         InjectArgs a{};
         a.S = S;
         a.ppc = win_.ppc;
@@ -1305,12 +1329,7 @@ Status Engine<real, DIM>::window_shift() {
         HIP_OR_FAIL((launch_inject<real, DIM>(g_, p_, seg_, st_, ctr_, a, stream_)));
     }
     HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost, stream_));
-    HIP_OR_FAIL(hipStreamSynchronize(stream_));
-    long long per[kMaxSpecies];
-    St = live_counts(per);
-    if (St.code) return St;
-    npart_ = 0;
-    for (int s = 0; s < g_.nsp; ++s) npart_ += per[s];
+    npart_ = npart_bound_;   // for the repack threshold
     return Status{};
 }
 

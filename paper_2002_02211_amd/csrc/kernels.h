@@ -103,6 +103,15 @@ template <typename freal>
 hipError_t launch_shift_x(const Geom& g, const freal* src, freal* dst, int S, hipStream_t stream);
 template <typename real, int DIM>
 hipError_t launch_shift_cells(const PArrays<real>& p, const Segs& seg, int S, int nseg, hipStream_t stream);
+// The segment table rotated by k tile columns into `to` (no aliasing with
+// `from`): segment d takes the start, capacity and count of the segment k
+// columns further along x; the last k columns take the slots of the first k
+// columns, with count 0.
+hipError_t launch_rotate_segments(const Geom& g, const Segs& from, const Segs& to, int k, hipStream_t stream);
+// Overflow-store particles moved S cells towards -x; those that thereby
+// leave the box are marked dead.  The store's size is read on the device.
+template <typename real, int DIM>
+hipError_t launch_shift_stash(const PArrays<real>& st, const int32_t* ctr, int S, hipStream_t stream);
 template <typename real, int DIM>
 hipError_t launch_inject(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
                          int32_t* ctr, const InjectArgs& a, hipStream_t stream);

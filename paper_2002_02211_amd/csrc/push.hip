@@ -693,6 +693,46 @@ k_shift_cells(PArrays<real> p, Segs seg, int S) {
     }
 }
 
+__global__ void __launch_bounds__(kBlock)
+k_rotate_segments(Geom g, Segs from, Segs to, int k) {
+    const int nseg = g.ntiles * g.nsp;
+    for (int d = blockIdx.x * kBlock + threadIdx.x; d < nseg; d += gridDim.x * kBlock) {
+        const int t = d / g.nsp, sp = d - t * g.nsp;
+        const int tx = t % g.nt[0];
+        const bool kept = tx < g.nt[0] - k;
+        const int src = (t - tx + (kept ? tx + k : tx - (g.nt[0] - k))) * g.nsp + sp;
+        to.start[d] = from.start[src];
+        to.cap[d] = from.cap[src];
+        to.count[d] = kept ? from.count[src] : 0;
+    }
+}
+
+hipError_t launch_rotate_segments(const Geom& g, const Segs& from, const Segs& to, int k, hipStream_t stream) {
+    const int nseg = g.ntiles * g.nsp;
+    const int blocks = std::min((nseg + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_rotate_segments, dim3(blocks), dim3(kBlock), 0, stream, g, from, to, k);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_shift_stash(PArrays<real> st, const int32_t* __restrict__ ctr, int S) {
+    const int n = ctr[CTR_STASH];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int32_t cell = st.cell[i];
+        if (cell == kDeadCell) continue;
+        int c[3];
+        unpack_cell<DIM>(cell, c[0], c[1], c[2]);
+        st.cell[i] = c[0] < S ? kDeadCell : pack_cell<DIM>(c[0] - S, c[1], c[2]);
+    }
+}
+
+template <typename real, int DIM>
+hipError_t launch_shift_stash(const PArrays<real>& st, const int32_t* ctr, int S, hipStream_t stream) {
+    hipLaunchKernelGGL((k_shift_stash<real, DIM>), dim3(256), dim3(kBlock), 0, stream, st, ctr, S);
+    return hipGetLastError();
+}
+
 // Cold plasma in the last S columns: thread idx is particle q of column col,
 // row (cy, cz), species sp, with idx = (((sp nz + cz) ny + cy) S + col) ppc + q.
 // A cell whose centre sees no density (lab frame) gets no particles.  Each
@@ -839,6 +879,7 @@ hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p
 
 #define SPINPIC_WINDOW_INST(real, DIM)                                                                        \
     template hipError_t launch_shift_cells<real, DIM>(const PArrays<real>&, const Segs&, int, int, hipStream_t); \
+    template hipError_t launch_shift_stash<real, DIM>(const PArrays<real>&, const int32_t*, int, hipStream_t); \
     template hipError_t launch_inject<real, DIM>(const Geom&, const PArrays<real>&, const Segs&,               \
                                                  const PArrays<real>&, int32_t*, const InjectArgs&, hipStream_t);
 SPINPIC_WINDOW_INST(float, 2)

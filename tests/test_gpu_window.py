@@ -6,6 +6,7 @@ oracle's window (oracle.Sim(window=...)).
   shifts: uniform injection with 16-cell tiles, a density ramp starting
   inside the injected region with 8-cell tiles, a fixed box with open faces
   (particles leaving), and 3D with a ragged last tile column.
+* Shifts with particles in the overflow store (segments without slack).
 * FP32: within the float32-storage bound of the oracle.
 * Bad parameters are rejected.
 * c2 at full size (FP32, the bench's tiles): right after a shift the newest
@@ -120,6 +121,39 @@ def test_window_opened_after_periodic_steps():
     worst, st = _compare(sim, ref, spec, 1e-9, "late window")
     _say("late window shifts", st["shifts"], "worst particle error %.2e" % worst)
     assert ref.shifts >= 1
+    sim.close()
+
+
+@pytest.mark.parametrize("shift_cells,speed,ppc,steps", [(8, 2.0, 2, 40), (64, 16.0, 4, 20)],
+                         ids=["one-column", "most-columns"])
+def test_window_shifts_with_a_full_overflow_store(shift_cells, speed, ppc, steps):
+    """Segments sized with almost no slack: injected particles spill into
+    the overflow store, which the shifts move along with the rest instead of
+    folding it back first; with shifts of most of the box its particles in
+    the first columns leave (and the stores grow)."""
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    win = _win(speed=speed, shift_cells=shift_cells, ppc=ppc, n0=0.03)
+    _say("window fp64 with overflow at the shifts", shift_cells, speed)
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp64", tile=(8, 8, 1), slack=1e-6),
+                       state["particles"], state["fields"])
+    sim.window(**win)
+    ref = oracle.Sim(spec, state, window=win)
+    spilled = 0
+    prev = sim.stats()
+    for n in range(1, steps + 1):
+        sim.step(1)
+        ref.step(1)
+        st = sim.stats()
+        if st["shifts"] > prev["shifts"]:
+            spilled = max(spilled, prev["overflow"])
+        prev = st
+        if n % 10 == 0:
+            worst, _ = _compare(sim, ref, spec, 1e-9, "overflow at shifts")
+            _say("step", n, "shifts", st["shifts"], "overflow", st["overflow"], "repacks", st["repacks"],
+                 "worst particle error %.2e" % worst)
+    assert ref.shifts >= 3
+    assert spilled > 0, "no shift happened with particles in the overflow store"
     sim.close()
 
 
