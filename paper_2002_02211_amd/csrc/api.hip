@@ -333,6 +333,10 @@ private:
     int resid_blocks_ = 0;
     int32_t* nf_flag_ = nullptr;
     freal* jbuf_[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    // the fused Yee step writes the new E and B here; the pointers are then
+    // swapped with f_'s
+    freal* enext_[3] = {nullptr, nullptr, nullptr};
+    freal* bnext_[3] = {nullptr, nullptr, nullptr};
     int jcur_ = 0;                 // buffer holding the last step's current
     long long store_cap_ = 0;      // slots of the leaver and overflow stores
     // moving window
@@ -590,6 +594,10 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         f_.B[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
         for (int b = 0; b < 2; ++b) jbuf_[b][a] = (freal*)dalloc(g_.ncells * sizeof(freal));
         f_.J[a] = jbuf_[0][a];
+        if (deposit_) {
+            enext_[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
+            bnext_[a] = (freal*)dalloc(g_.ncells * sizeof(freal));
+        }
     }
     ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
     moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
@@ -601,7 +609,8 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     nf_flag_ = (int32_t*)dalloc(sizeof(int32_t));
     bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && acc_ && rho_ && ref_ &&
               blockmax_ && nf_flag_;
-    for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
+    for (int a = 0; a < 3; ++a)
+        ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a] && (!deposit_ || (enext_[a] && bnext_[a]));
     if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
     HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
     std::memset(h_ctr_, 0, CTR_NCTR * sizeof(int32_t));
@@ -735,9 +744,25 @@ Status Engine<real, DIM>::step(int nsteps) {
         tstop(2);
         if (deposit_) {
             tstart(3);
-            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 0, stream_)));
-            HIP_OR_FAIL((launch_fdtd_e<freal, DIM>(g_, kf_, f_, jbuf_[jcur_], stream_)));
-            HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 1, stream_)));
+            if (!g_.open_x) {
+                // periodic: one fused pass into the spare arrays
+                Fields<freal> nf = f_;
+                for (int a = 0; a < 3; ++a) {
+                    nf.E[a] = enext_[a];
+                    nf.B[a] = bnext_[a];
+                }
+                HIP_OR_FAIL((launch_yee_fused<freal, DIM>(g_, kf_, f_, nf, jbuf_[jcur_], stream_)));
+                for (int a = 0; a < 3; ++a) {
+                    std::swap(f_.E[a], enext_[a]);
+                    std::swap(f_.B[a], bnext_[a]);
+                }
+            } else {
+                // open x faces: the Mur ghosts are advanced between the
+                // three updates, in place
+                HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 0, stream_)));
+                HIP_OR_FAIL((launch_fdtd_e<freal, DIM>(g_, kf_, f_, jbuf_[jcur_], stream_)));
+                HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 1, stream_)));
+            }
             tstop(3);
         }
         HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),

@@ -132,6 +132,249 @@ k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
     fdtd_e_at<real, DIM>(g, k, f, jclear, i, j, blockIdx.z);
 }
 
+// ---------------------------------------------------------------- fused Yee step
+
+// The whole Yee step of periodic fields in one pass: B' = B - (dt/2) curl E,
+// E_out = E + dt (curl B' - J), B_out = B' - (dt/2) curl E_out, with the same
+// differences as k_fdtd_b and k_fdtd_e.  The step reads E, B and J once and
+// writes E_out and B_out once (the input arrays are not written: other
+// workgroups still read them as guard cells).
+//
+// A workgroup owns an in-plane block of cells (x, plus y in 3D) and a run of
+// M planes along the marching axis (y in 2D, z in 3D).  It walks the planes
+// p = m0 - 1 .. m0 + M keeping two planes of E, B' and E_out in shared
+// memory: at plane p it loads E(p + 1), computes B'(p) (which needs E(p) and
+// E(p + 1)), then E_out(p) (which needs B'(p) and B'(p - 1)), then B_out(p -
+// 1) (which needs E_out(p - 1) and E_out(p)).  Differences inside a plane
+// reach one cell: E is held on the block widened by 1 below and 2 above, B'
+// by 1 on both sides, E_out by 1 above.
+template <int DIM>
+struct YeeBlock;
+template <>
+struct YeeBlock<2> {
+    static constexpr int RX = 253, RY = 1, M = 8;
+};
+template <>
+struct YeeBlock<3> {
+    static constexpr int RX = 32, RY = 4, M = 16;
+};
+
+template <int DIM>
+struct YeeDims {
+    static constexpr int RX = YeeBlock<DIM>::RX, RY = YeeBlock<DIM>::RY;
+    static constexpr int EX = RX + 3, EY = DIM == 3 ? RY + 3 : 1;   // E: origin (-1, -1)
+    static constexpr int BX = RX + 2, BY = DIM == 3 ? RY + 2 : 1;   // B': origin (-1, -1)
+    static constexpr int FX = RX + 1, FY = DIM == 3 ? RY + 1 : 1;   // E_out: origin (0, 0)
+    static constexpr int NE = EX * EY, NB = BX * BY, NF = FX * FY;
+};
+
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jclear, int tiles_u, int chunks) {
+    using D = YeeDims<DIM>;
+    constexpr int RX = D::RX, RY = D::RY, M = YeeBlock<DIM>::M;
+    static_assert(D::NE <= kBlock, "one E cell per thread");
+    __shared__ real sE[2][3][D::NE];
+    __shared__ real sB[2][3][D::NB];
+    __shared__ real sF[2][3][D::NF];
+
+    // Consecutive block numbers go to one XCD (workgroups are dealt
+    // round-robin over the 8 XCDs) and walk the in-plane blocks of one run
+    // of planes before the next run, so the blocks that run side by side
+    // are in-plane neighbours whose guard cells meet in that XCD's L2.
+    const int ntile = tiles_u * (DIM == 3 ? (g.n[1] + RY - 1) / RY : 1);
+    const int nblk = ntile * chunks;
+    const int per = (nblk + 7) >> 3;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= nblk) return;
+    const int chunk = b / ntile;
+    const int tile = b - chunk * ntile;
+    const int x0 = (tile % tiles_u) * RX;
+    const int y0 = DIM == 3 ? (tile / tiles_u) * RY : 0;
+    const int nx = g.n[0], ny = g.n[1];
+    const int nw = DIM == 3 ? g.n[2] : g.n[1];        // planes along the marching axis
+    const long long pstride = DIM == 3 ? (long long)nx * ny : nx;
+    const int m0 = chunk * M;
+    const int mend = min(m0 + M, nw);
+    const int t = threadIdx.x;
+
+    // Thread t holds cell t of each of the E, B' and E_out tiles and of the
+    // block; its in-plane offsets are fixed (periodic wrap).
+    auto inplane = [&](int u, int v) -> long long {
+        const int x = wrap_index(x0 + u, nx);
+        if (DIM == 3) return (long long)wrap_index(y0 + v, ny) * nx + x;
+        return x;
+    };
+    auto plane = [&](int w) -> long long { return (long long)wrap_index(w, nw) * pstride; };
+    const bool hasE = t < D::NE, hasB = t < D::NB, hasF = t < D::NF;
+    // threads without a cell load cell 0 of the tile (every lane loads, so
+    // the loads in flight are counted the same on every path)
+    const int te = hasE ? t : 0, tb = hasB ? t : 0, tf = hasF ? t : 0;
+    const long long offE = inplane(te % D::EX - 1, te / D::EX - 1);
+    const long long offB = inplane(tb % D::BX - 1, tb / D::BX - 1);
+    const int fu = tf % D::FX, fv = tf / D::FX;
+    const long long offF = inplane(fu, fv);
+    const bool ownF = hasF && fu < RX && fv < RY && x0 + fu < nx && (DIM == 2 || y0 + fv < ny);
+    const int ou = t % RX, ov = t / RX;
+    const bool ownO = t < RX * RY && x0 + ou < nx && (DIM == 2 || y0 + ov < ny);
+    const long long offO = inplane(ou, ov);
+
+    // Inputs of plane p (E(p + 1), B(p), J(p)) are loaded two planes ahead
+    // into one of two register sets, used by turns (the loop is unrolled by
+    // two so that each set keeps its registers).
+    struct PlaneIn {
+        real E[3], B[3], J[3];
+    };
+    // each part is loaded again as soon as its last value has been used, so
+    // the new values can take the old ones' registers
+    auto load_E = [&](PlaneIn& q, int p) {
+        const long long c = plane(p + 1) + offE;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.E[a] = f.E[a][c];
+    };
+    auto load_B = [&](PlaneIn& q, int p) {
+        const long long c = plane(p) + offB;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.B[a] = f.B[a][c];
+    };
+    auto load_J = [&](PlaneIn& q, int p) {
+        const long long c = plane(p) + offF;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q.J[a] = f.J[a][c];
+    };
+
+    auto step = [&](int p, PlaneIn& q) {
+        const int s0 = (p + 2) & 1, s1 = (p + 3) & 1, sm = (p + 1) & 1;   // planes p, p + 1, p - 1
+        // (loads run past the run's end too, so every path has the same
+        // loads in flight)
+        if (hasE) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sE[s1][a][t] = q.E[a];
+        }
+        load_E(q, p + 2);
+        __syncthreads();
+        // B'(p) on the block widened by 1
+        if (hasB) {
+            const int e = (t / D::BX) * D::EX + t % D::BX;   // same cell in the E tile
+            const real ex = sE[s0][0][e], ey = sE[s0][1][e], ez = sE[s0][2][e];
+            const real eyp = sE[s0][1][e + 1], ezp = sE[s0][2][e + 1];      // +x
+            real ezy, exy;                                                   // +y
+            if (DIM == 3) {
+                ezy = sE[s0][2][e + D::EX];
+                exy = sE[s0][0][e + D::EX];
+            } else {
+                ezy = sE[s1][2][e];
+                exy = sE[s1][0][e];
+            }
+            real cx = k.cb[1] * (ezy - ez);
+            real cy = -k.cb[0] * (ezp - ez);
+            const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
+            if (DIM == 3) {
+                cx -= k.cb[2] * (sE[s1][1][e] - ey);
+                cy += k.cb[2] * (sE[s1][0][e] - ex);
+            }
+            sB[s0][0][t] = q.B[0] - cx;
+            sB[s0][1][t] = q.B[1] - cy;
+            sB[s0][2][t] = q.B[2] - cz;
+        }
+        load_B(q, p + 2);
+        __syncthreads();
+        if (p >= m0) {
+            // E_out(p) on the block widened by 1 above
+            if (hasF) {
+                const int r = fv + (DIM == 3 ? 1 : 0);
+                const int bb = r * D::BX + fu + 1;   // same cell in the B' tile
+                const int e = r * D::EX + fu + 1;    // and in the E tile
+                const real bx = sB[s0][0][bb], by = sB[s0][1][bb], bz = sB[s0][2][bb];
+                const real bym = sB[s0][1][bb - 1], bzm = sB[s0][2][bb - 1];   // -x
+                real bzy, bxy;                                                  // -y
+                if (DIM == 3) {
+                    bzy = sB[s0][2][bb - D::BX];
+                    bxy = sB[s0][0][bb - D::BX];
+                } else {
+                    bzy = sB[sm][2][bb];
+                    bxy = sB[sm][0][bb];
+                }
+                real cx = k.ce[1] * (bz - bzy);
+                real cy = -k.ce[0] * (bz - bzm);
+                const real cz = k.ce[0] * (by - bym) - k.ce[1] * (bx - bxy);
+                if (DIM == 3) {
+                    cx -= k.ce[2] * (by - sB[sm][1][bb]);
+                    cy += k.ce[2] * (bx - sB[sm][0][bb]);
+                }
+                const real e0 = sE[s0][0][e] + (cx - k.dt * q.J[0]);
+                const real e1 = sE[s0][1][e] + (cy - k.dt * q.J[1]);
+                const real e2 = sE[s0][2][e] + (cz - k.dt * q.J[2]);
+                sF[s0][0][t] = e0;
+                sF[s0][1][t] = e1;
+                sF[s0][2][t] = e2;
+                if (ownF && p < mend) {
+                    const long long c = plane(p) + offF;
+                    out.E[0][c] = e0;
+                    out.E[1][c] = e1;
+                    out.E[2][c] = e2;
+                    if (jclear.c[0]) {
+                        static_cast<real*>(jclear.c[0])[c] = real(0);
+                        static_cast<real*>(jclear.c[1])[c] = real(0);
+                        static_cast<real*>(jclear.c[2])[c] = real(0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        load_J(q, p + 2);
+        if (p > m0 && p <= mend && ownO) {
+            // B_out(p - 1) on the block
+            const int fi = ov * D::FX + ou;                                  // E_out tile
+            const int bb = (ov + (DIM == 3 ? 1 : 0)) * D::BX + ou + 1;       // B' tile
+            const real ex = sF[sm][0][fi], ey = sF[sm][1][fi], ez = sF[sm][2][fi];
+            const real eyp = sF[sm][1][fi + 1], ezp = sF[sm][2][fi + 1];    // +x
+            real ezy, exy;                                                   // +y
+            if (DIM == 3) {
+                ezy = sF[sm][2][fi + D::FX];
+                exy = sF[sm][0][fi + D::FX];
+            } else {
+                ezy = sF[s0][2][fi];
+                exy = sF[s0][0][fi];
+            }
+            real cx = k.cb[1] * (ezy - ez);
+            real cy = -k.cb[0] * (ezp - ez);
+            const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
+            if (DIM == 3) {
+                cx -= k.cb[2] * (sF[s0][1][fi] - ey);
+                cy += k.cb[2] * (sF[s0][0][fi] - ex);
+            }
+            const long long c = plane(p - 1) + offO;
+            out.B[0][c] = sB[sm][0][bb] - cx;
+            out.B[1][c] = sB[sm][1][bb] - cy;
+            out.B[2][c] = sB[sm][2][bb] - cz;
+        }
+    };
+
+    if (hasE) {
+        const long long c = plane(m0 - 1) + offE;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sE[(m0 + 1) & 1][a][t] = f.E[a][c];
+    }
+    PlaneIn qa, qb;
+    load_E(qa, m0 - 1);
+    load_B(qa, m0 - 1);
+    load_J(qa, m0 - 1);
+    load_E(qb, m0);
+    load_B(qb, m0);
+    load_J(qb, m0);
+    // planes m0 - 1 .. m0 + M, a fixed count, fully unrolled: no loop
+    // header at which the loads in flight would have to be waited for.  A
+    // run cut short by the end of the grid computes its last planes on
+    // wrapped data and writes nothing there.
+    static_assert(M % 2 == 0, "an even number of steps");
+#pragma unroll
+    for (int i = 0; i < (M + 2) / 2; ++i) {
+        step(m0 - 1 + 2 * i, qa);
+        step(m0 + 2 * i, qb);
+    }
+}
+
 // Moving window: dst = src moved S cells towards -x, zero in the last S columns.
 template <typename freal>
 __global__ void __launch_bounds__(kBlock)
@@ -495,6 +738,25 @@ hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t st
 }
 
 template <typename real, int DIM>
+hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<real>& f, const Fields<real>& out,
+                            real* const* jclear, hipStream_t stream) {
+    if (g.open_x) return hipErrorInvalidValue;   // open faces take the three-kernel step
+    JClear jc{{nullptr, nullptr, nullptr}};
+    if (jclear)
+        for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
+    constexpr int RX = YeeBlock<DIM>::RX, RY = YeeBlock<DIM>::RY, M = YeeBlock<DIM>::M;
+    const int tiles_u = (g.n[0] + RX - 1) / RX;
+    const int tiles_v = DIM == 3 ? (g.n[1] + RY - 1) / RY : 1;
+    const int nw = DIM == 3 ? g.n[2] : g.n[1];
+    const int chunks = (nw + M - 1) / M;
+    const long long nblk = (long long)tiles_u * tiles_v * chunks;
+    const long long grid = (nblk + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), 0, stream, g, k, f, out, jc,
+                       tiles_u, chunks);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
 hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
                          real* const* jclear, hipStream_t stream) {
     JClear jc{{nullptr, nullptr, nullptr}};
@@ -586,6 +848,8 @@ hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStr
 #define SPINPIC_INST_GRID(DIM)                                                                 \
     template hipError_t launch_fdtd_b<double, DIM>(const Geom&, const Consts<double>&,        \
                                                    const Fields<double>&, int, hipStream_t);   \
+    template hipError_t launch_yee_fused<double, DIM>(const Geom&, const Consts<double>&,     \
+        const Fields<double>&, const Fields<double>&, double* const*, hipStream_t);             \
     template hipError_t launch_mur_reset<double, DIM>(const Geom&, const Fields<double>&,     \
                                                       hipStream_t);                            \
     template hipError_t launch_fdtd_e<double, DIM>(const Geom&, const Consts<double>&,        \

@@ -123,6 +123,13 @@ hipError_t launch_inject(const Geom& g, const PArrays<real>& p, const Segs& seg,
 template <typename real, int DIM>
 hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f, int update_hi,
                          hipStream_t stream);
+// The whole Yee step (B half step, E step with -dt J, B half step) of
+// periodic fields in one pass: reads f.E, f.B, f.J, writes out.E and out.B
+// (distinct arrays of the same size); zeroes jclear like launch_fdtd_e.
+// Returns hipErrorInvalidValue for open x faces.
+template <typename real, int DIM>
+hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<real>& f, const Fields<real>& out,
+                            real* const* jclear, hipStream_t stream);
 // Mur state of open x faces (f.mur) started from the current fields.
 template <typename real, int DIM>
 hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t stream);
