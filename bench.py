@@ -76,6 +76,9 @@ def algorithmic_bytes(ndim, precision, npart, ncells):
     return (read + write) * npart + grid * ncells, read + write, grid
 
 
+BREAKDOWN_STEPS = 20   # steps after the timed ones, with events around every kernel
+
+
 def source_hash():
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2002_02211_amd", "csrc", "*"))):
@@ -293,14 +296,18 @@ def _time_batch(S, cfgs, states, autotune, warmup, steps):
     print("[bench] batch init (autotune %s) %.1f s" % (autotune, t_init), file=sys.stderr, flush=True)
     b.step(warmup)
     torch.cuda.synchronize()
-    b.timing(True)
+    b.timing(True, push_only=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timers = b.timing_read()
+    b.timing(True)
+    b.step(BREAKDOWN_STEPS)
+    rest = b.timing_read()
     b.timing(False)
+    timers = {k: (timers[k] if k == "push_deposit" else rest[k]) for k in timers}
     print("[bench] batch (autotune %s) timed %d steps in %.3f s" % (autotune, steps, elapsed),
           file=sys.stderr, flush=True)
     return b, t_init, elapsed, timers
@@ -392,7 +399,7 @@ def _batch_comparisons(S, specs, cfgs, pairs, tiles, launch_bytes, npart, args):
         cfg = S.config_from_spec(s, precision="fp32", tile=tiles[r] + (1,))
         sim = S.Simulation(cfg, parts, fields)
         sim.step(args.warmup)
-        sim.timing(True)
+        sim.timing(True, push_only=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sim.step(args.steps)
@@ -461,14 +468,21 @@ def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None, window=Fal
     sim.step(warmup)
     torch.cuda.synchronize()
     print("[bench] %s warmup done" % precision, file=sys.stderr, flush=True)
-    sim.timing(True)
+    # events around the push kernel only in the timed region (events between
+    # every kernel would lengthen the step); the other kernels' times come
+    # from BREAKDOWN_STEPS further steps
+    sim.timing(True, push_only=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timers = sim.timing_read()
+    sim.timing(True)
+    sim.step(BREAKDOWN_STEPS)
+    rest = sim.timing_read()
     sim.timing(False)
+    timers = {k: (timers[k] if k == "push_deposit" else rest[k]) for k in timers}
     return sim, cfg, elapsed, timers
 
 
@@ -622,7 +636,7 @@ def main():
             "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
             "dP_max_fp32_vs_fp64": float(np.max(np.abs(np.asarray(P) - np.asarray(P64)))),
             "P_fp32": [float(v) for v in P], "P_fp64": [float(v) for v in P64],
-            "after_steps": args.warmup + args.steps}
+            "after_steps": args.warmup + args.steps + BREAKDOWN_STEPS}
 
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, min(p.shape[0] for p in state["particles"]))

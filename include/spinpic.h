@@ -244,7 +244,10 @@ typedef struct {
 int pic_window(pic_ctx* ctx, const pic_window_config* w);
 
 /* Per-kernel GPU timing with HIP events on the context's stream.
- * pic_timing(ctx, 1) starts (and resets) recording, 0 stops it.
+ * pic_timing(ctx, 1) starts (and resets) recording of every kernel class,
+ * pic_timing(ctx, 2) of the push+deposit kernel only (no events between the
+ * other kernels of a step, whose launches then follow each other without
+ * them), 0 stops it; other values are PIC_EINVAL.
  * pic_timing_read fills ms_out[k] (total milliseconds) and launches_out[k]
  * for k = 0 push+deposit (including the compaction of the slots tile
  * leavers vacate), 1 overflow push, 2 insertion of tile leavers, 3 field

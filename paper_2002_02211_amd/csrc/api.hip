@@ -150,6 +150,7 @@ constexpr int kTimers = 4;   // push+deposit, overflow push, insertion, field up
 
 struct Timer {
     bool on = false;
+    unsigned mask = 0;   // kernel classes recorded (bit k: class k)
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> rec;
     size_t used = 0;
@@ -158,7 +159,7 @@ struct Timer {
 // HIP events around each kernel class on a stream: start/stop pairs recorded
 // while on, summed per class by timer_read.
 void timer_start(Timer& tm, hipStream_t stream, int k) {
-    if (!tm.on) return;
+    if (!tm.on || !((tm.mask >> k) & 1u)) return;
     if (tm.used + 2 > tm.pool.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
@@ -178,8 +179,10 @@ void timer_stop(Timer& tm, hipStream_t stream, int k) {
 }
 
 Status timer_enable(Timer& tm, hipStream_t stream, int enable) {
+    if (enable < 0 || enable > 2) return fail(PIC_EINVAL, "timing mode %d is not 0, 1 or 2", enable);
     HIP_OR_FAIL(hipStreamSynchronize(stream));
     tm.on = enable != 0;
+    tm.mask = enable == 2 ? 1u : (1u << kTimers) - 1u;
     tm.rec.clear();
     tm.used = 0;
     return Status{};
@@ -765,8 +768,11 @@ Status Engine<real, DIM>::step(int nsteps) {
             }
             tstop(3);
         }
-        HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, stream_));
+        // the overflow count for the next check (read only there: a copy
+        // every step would cost a transfer and two launch gaps per step)
+        if ((nstep_ + 1) % kStashCheck == 0)
+            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
         ++nstep_;
@@ -1889,7 +1895,10 @@ Status BatchEngine<real>::step(int nsteps) {
             HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, stream_)));
             timer_stop(timer_, stream_, 3);
         }
-        HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t), hipMemcpyDeviceToHost, stream_));
+        // the overflow count for the next check only
+        if ((nstep_ + 1) % kStashCheck == 0)
+            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
         ++nstep_;

@@ -361,8 +361,13 @@ def pic_window(ctx, w):
     _check(load_library().pic_window(ctx, ctypes.byref(w)), ctx)
 
 
-def pic_timing(ctx, enable):
-    _check(load_library().pic_timing(ctx, int(bool(enable))), ctx)
+def _timing_mode(enable, push_only):
+    return 0 if not enable else (2 if push_only else 1)
+
+
+def pic_timing(ctx, enable, push_only=False):
+    """Start (every kernel class, or the push only) or stop event timing."""
+    _check(load_library().pic_timing(ctx, _timing_mode(enable, push_only)), ctx)
 
 
 TIMER_NAMES = ("push_deposit", "overflow_push", "insert", "fdtd")
@@ -431,8 +436,8 @@ class Simulation:
     def stats(self):
         return pic_stats(self.ctx)
 
-    def timing(self, enable=True):
-        pic_timing(self.ctx, enable)
+    def timing(self, enable=True, push_only=False):
+        pic_timing(self.ctx, enable, push_only)
 
     def timing_read(self):
         return pic_timing_read(self.ctx)
@@ -642,8 +647,8 @@ class Batch:
         return {"steps": out[0], "moved": out[1], "overflow": out[2], "repacks": out[3],
                 "particles": out[4], "push_workgroups": out[5], "tiles": out[6]}
 
-    def timing(self, enable=True):
-        _batch_check(load_library().pic_batch_timing(self.h, 1 if enable else 0), self.h)
+    def timing(self, enable=True, push_only=False):
+        _batch_check(load_library().pic_batch_timing(self.h, _timing_mode(enable, push_only)), self.h)
 
     def timing_read(self):
         ms = np.zeros(4)

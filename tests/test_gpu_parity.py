@@ -299,3 +299,23 @@ def test_state_errors_after_free():
     assert ei.value.code == S.PIC_EINVAL
     sim.step(2)   # still usable after argument errors
     sim.close()
+
+
+def test_timing_modes():
+    """pic_timing: mode 1 records every kernel class each step, mode 2 the
+    push only; other modes are rejected."""
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    sim = S.Simulation(S.config_from_spec(spec), state["particles"], state["fields"])
+    _say("timing modes")
+    sim.timing(True, push_only=True)
+    sim.step(3)
+    t = sim.timing_read()
+    assert t["push_deposit"][1] == 3 and t["push_deposit"][0] > 0
+    assert all(t[k][1] == 0 for k in ("overflow_push", "insert", "fdtd"))
+    sim.timing(True)
+    sim.step(2)
+    t = sim.timing_read()
+    assert all(t[k][1] == 2 for k in S.TIMER_NAMES)
+    assert S.load_library().pic_timing(sim.ctx, 3) == S.PIC_EINVAL
+    sim.close()
