@@ -251,7 +251,8 @@ int pic_window(pic_ctx* ctx, const pic_window_config* w);
  * pic_timing_read fills ms_out[k] (total milliseconds) and launches_out[k]
  * for k = 0 push+deposit (including the compaction of the slots tile
  * leavers vacate), 1 overflow push, 2 insertion of tile leavers, 3 field
- * update (all three Yee kernels of a step); cap >= 4.  Waits. */
+ * update (the fused Yee pass, or its three kernels with open x faces);
+ * cap >= 4.  Waits. */
 int pic_timing(pic_ctx* ctx, int32_t enable);
 int pic_timing_read(pic_ctx* ctx, double* ms_out, int64_t* launches_out, int32_t cap);
 

@@ -1412,7 +1412,7 @@ public:
         Geom g;
         double d[3];
         long long cell_off = 0;
-        int sid_base = 0, tile_base = 0, fdtd_blk_base = 0;
+        int sid_base = 0, tile_base = 0, yee_blk_base = 0;
         long long count_sp[kMaxSpecies] = {0, 0, 0, 0};
         long long npart = 0;
     };
@@ -1492,7 +1492,10 @@ private:
     TileRef* d_order_ = nullptr;
     XcdQueues xq_{};
     int32_t* d_blk_run_ = nullptr;   // field-update block -> run
-    int fdtd_nblk_ = 0;
+    int yee_nblk_ = 0;
+    // the fused Yee step writes the new E and B here (pointers then swapped)
+    freal* enext_[3] = {nullptr, nullptr, nullptr};
+    freal* bnext_[3] = {nullptr, nullptr, nullptr};
     std::vector<TileRef> order_;
     Timer timer_;
 };
@@ -1569,7 +1572,7 @@ Status BatchEngine<real>::upload_descs() {
         D.cell_off = R.cell_off;
         D.sid_base = R.sid_base;
         D.tile_base = R.tile_base;
-        D.fdtd_blk_base = R.fdtd_blk_base;
+        D.yee_blk_base = R.yee_blk_base;
     }
     HIP_OR_FAIL(hipMemcpyAsync(d_runs_, d.data(), d.size() * sizeof(RunDesc<real>), hipMemcpyHostToDevice, stream_));
     return Status{};
@@ -1604,10 +1607,10 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
         R.cell_off = cells;
         R.sid_base = sids;
         R.tile_base = tiles;
-        R.fdtd_blk_base = fdtd_nblk_;
-        if ((long long)fdtd_nblk_ + fdtd_blocks(R.g.n[0], R.g.n[1]) > (1LL << 30))
+        R.yee_blk_base = yee_nblk_;
+        if ((long long)yee_nblk_ + yee_blocks(R.g.n[0], R.g.n[1]) > (1LL << 30))
             return fail(PIC_EINVAL, "batch too large for one field-update launch");
-        fdtd_nblk_ += fdtd_blocks(R.g.n[0], R.g.n[1]);
+        yee_nblk_ += yee_blocks(R.g.n[0], R.g.n[1]);
         cells += R.g.ncells;
         sids += R.g.ntiles * nsp_;
         tiles += R.g.ntiles;
@@ -1710,6 +1713,10 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
         f_.B[a] = (freal*)dalloc(ncells_ * sizeof(freal));
         for (int b = 0; b < 2; ++b) jbuf_[b][a] = (freal*)dalloc(ncells_ * sizeof(freal));
         f_.J[a] = jbuf_[0][a];
+        if (deposit_) {
+            enext_[a] = (freal*)dalloc(ncells_ * sizeof(freal));
+            bnext_[a] = (freal*)dalloc(ncells_ * sizeof(freal));
+        }
     }
     ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
     moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
@@ -1717,10 +1724,11 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     acc_ = (double*)dalloc(8 * sizeof(double));
     d_runs_ = (RunDesc<real>*)dalloc(nrun * sizeof(RunDesc<real>));
     d_order_ = (TileRef*)dalloc(ntiles_ * sizeof(TileRef));
-    d_blk_run_ = (int32_t*)dalloc((size_t)fdtd_nblk_ * sizeof(int32_t));
+    d_blk_run_ = (int32_t*)dalloc((size_t)yee_nblk_ * sizeof(int32_t));
     bool ok = seg_.start && seg_.cap && seg_.count && ctr_ && moved_ && run_ns_ && acc_ && d_runs_ && d_order_ &&
               d_blk_run_;
-    for (int a = 0; a < 3; ++a) ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a];
+    for (int a = 0; a < 3; ++a)
+        ok = ok && f_.E[a] && f_.B[a] && jbuf_[0][a] && jbuf_[1][a] && (!deposit_ || (enext_[a] && bnext_[a]));
     if (!ok) return fail(PIC_ENOMEM, "device allocation failed");
     HIP_OR_FAIL(hipHostMalloc((void**)&h_ctr_, CTR_NCTR * sizeof(int32_t), hipHostMallocDefault));
     std::memset(h_ctr_, 0, CTR_NCTR * sizeof(int32_t));
@@ -1836,11 +1844,11 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     }
     HIP_OR_FAIL(hipMemcpyAsync(d_order_, order_.data(), ntiles_ * sizeof(TileRef), hipMemcpyHostToDevice, stream_));
     {
-        std::vector<int32_t> blk_run((size_t)fdtd_nblk_);
+        std::vector<int32_t> blk_run((size_t)yee_nblk_);
         for (int r = 0; r < nrun; ++r) {
             const Run& R = runs_[r];
-            std::fill(blk_run.begin() + R.fdtd_blk_base,
-                      blk_run.begin() + R.fdtd_blk_base + fdtd_blocks(R.g.n[0], R.g.n[1]), r);
+            std::fill(blk_run.begin() + R.yee_blk_base,
+                      blk_run.begin() + R.yee_blk_base + yee_blocks(R.g.n[0], R.g.n[1]), r);
         }
         HIP_OR_FAIL(hipMemcpyAsync(d_blk_run_, blk_run.data(), blk_run.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, stream_));
@@ -1890,9 +1898,16 @@ Status BatchEngine<real>::step(int nsteps) {
         timer_stop(timer_, stream_, 2);
         if (deposit_) {
             timer_start(timer_, stream_, 3);
-            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, stream_)));
-            HIP_OR_FAIL((launch_fdtd_e_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, jbuf_[jcur_], stream_)));
-            HIP_OR_FAIL((launch_fdtd_b_batch<real>(d_runs_, d_blk_run_, fdtd_nblk_, f_, stream_)));
+            Fields<freal> nf = f_;
+            for (int a = 0; a < 3; ++a) {
+                nf.E[a] = enext_[a];
+                nf.B[a] = bnext_[a];
+            }
+            HIP_OR_FAIL((launch_yee_fused_batch<real>(d_runs_, d_blk_run_, yee_nblk_, f_, nf, jbuf_[jcur_], stream_)));
+            for (int a = 0; a < 3; ++a) {
+                std::swap(f_.E[a], enext_[a]);
+                std::swap(f_.B[a], bnext_[a]);
+            }
             timer_stop(timer_, stream_, 3);
         }
         // the overflow count for the next check only

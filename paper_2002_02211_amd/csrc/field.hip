@@ -168,9 +168,25 @@ struct YeeDims {
     static constexpr int NE = EX * EY, NB = BX * BY, NF = FX * FY;
 };
 
+// Blocks of one grid: in-plane blocks across, runs of planes down.
+template <int DIM>
+__host__ __device__ inline int yee_tiles_u(const Geom& g) { return (g.n[0] + YeeBlock<DIM>::RX - 1) / YeeBlock<DIM>::RX; }
+template <int DIM>
+__host__ __device__ inline int yee_tiles(const Geom& g) {
+    return yee_tiles_u<DIM>(g) * (DIM == 3 ? (g.n[1] + YeeBlock<DIM>::RY - 1) / YeeBlock<DIM>::RY : 1);
+}
+template <int DIM>
+__host__ __device__ inline int yee_chunks(const Geom& g) {
+    return ((DIM == 3 ? g.n[2] : g.n[1]) + YeeBlock<DIM>::M - 1) / YeeBlock<DIM>::M;
+}
+
+// Block b (0 <= b < yee_tiles * yee_chunks) of one grid's fused Yee step.
+// Consecutive b walk the in-plane blocks of one run of planes before the
+// next run.  Every thread of the workgroup must call it.
 template <typename real, int DIM>
-__global__ void __launch_bounds__(kBlock)
-k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jclear, int tiles_u, int chunks) {
+__device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, const Consts<real>& k,
+                                                               const Fields<real>& f, const Fields<real>& out,
+                                                               const JClear& jclear, int b) {
     using D = YeeDims<DIM>;
     constexpr int RX = D::RX, RY = D::RY, M = YeeBlock<DIM>::M;
     static_assert(D::NE <= kBlock, "one E cell per thread");
@@ -178,15 +194,8 @@ k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jcl
     __shared__ real sB[2][3][D::NB];
     __shared__ real sF[2][3][D::NF];
 
-    // Consecutive block numbers go to one XCD (workgroups are dealt
-    // round-robin over the 8 XCDs) and walk the in-plane blocks of one run
-    // of planes before the next run, so the blocks that run side by side
-    // are in-plane neighbours whose guard cells meet in that XCD's L2.
-    const int ntile = tiles_u * (DIM == 3 ? (g.n[1] + RY - 1) / RY : 1);
-    const int nblk = ntile * chunks;
-    const int per = (nblk + 7) >> 3;
-    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (b >= nblk) return;
+    const int tiles_u = yee_tiles_u<DIM>(g);
+    const int ntile = yee_tiles<DIM>(g);
     const int chunk = b / ntile;
     const int tile = b - chunk * ntile;
     const int x0 = (tile % tiles_u) * RX;
@@ -375,6 +384,19 @@ k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jcl
     }
 }
 
+// Consecutive block numbers go to one XCD (workgroups are dealt round-robin
+// over the 8 XCDs), so the blocks that run side by side are in-plane
+// neighbours whose guard cells meet in that XCD's L2.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jclear) {
+    const int nblk = yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
+    const int per = (nblk + 7) >> 3;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= nblk) return;
+    yee_fused_block<real, DIM>(g, k, f, out, jclear, b);
+}
+
 // Moving window: dst = src moved S cells towards -x, zero in the last S columns.
 template <typename freal>
 __global__ void __launch_bounds__(kBlock)
@@ -410,40 +432,22 @@ __device__ inline Fields<freal> offset_fields(const Fields<freal>& f, long long 
     return r;
 }
 
-// Block b of the batch's field update: its run, and the cell (i, j) of this
-// thread in that run (false outside the run's grid).
+// The fused Yee step of every run of a batch: one flat list of the runs'
+// blocks (yee_blocks(g) from runs[r].yee_blk_base on; blk_run[b] = r).
 template <typename real>
-__device__ inline bool batch_cell(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run,
-                                  int& run, int& i, int& j) {
-    static_assert(kFx == 64 && kFy == 4, "fdtd_blocks() assumes 64 x 4 blocks");
-    run = blk_run[blockIdx.x];
-    const int local = (int)blockIdx.x - runs[run].fdtd_blk_base;
-    const int bx = fdtd_blocks_x(runs[run].g.n[0]);
-    i = (local % bx) * kFx + (int)threadIdx.x;
-    j = (local / bx) * kFy + (int)threadIdx.y;
-    return i < runs[run].g.n[0] && j < runs[run].g.n[1];
-}
-
-template <typename real>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_b_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, Fields<freal> f) {
-    int run, i, j;
-    if (!batch_cell(runs, blk_run, run, i, j)) return;
-    const RunDesc<real>& rd = runs[run];
-    fdtd_b_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), i, j, 0, false);
-}
-
-template <typename real>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_e_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, Fields<freal> f,
-               JClear jclear) {
-    int run, i, j;
-    if (!batch_cell(runs, blk_run, run, i, j)) return;
+__global__ void __launch_bounds__(kBlock)
+k_yee_fused_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, int nblk,
+                  Fields<freal> f, Fields<freal> out, JClear jclear) {
+    const int per = (nblk + 7) >> 3;
+    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (b >= nblk) return;
+    const int run = blk_run[b];
     const RunDesc<real>& rd = runs[run];
     JClear jc = jclear;
     if (jc.c[0])
         for (int a = 0; a < 3; ++a) jc.c[a] = static_cast<freal*>(jc.c[a]) + rd.cell_off;
-    fdtd_e_at<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), jc, i, j, 0);
+    yee_fused_block<freal, 2>(rd.g, rd.kf, offset_fields<real>(f, rd.cell_off), offset_fields<real>(out, rd.cell_off),
+                              jc, b - rd.yee_blk_base);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -744,16 +748,18 @@ hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<r
     JClear jc{{nullptr, nullptr, nullptr}};
     if (jclear)
         for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
-    constexpr int RX = YeeBlock<DIM>::RX, RY = YeeBlock<DIM>::RY, M = YeeBlock<DIM>::M;
-    const int tiles_u = (g.n[0] + RX - 1) / RX;
-    const int tiles_v = DIM == 3 ? (g.n[1] + RY - 1) / RY : 1;
-    const int nw = DIM == 3 ? g.n[2] : g.n[1];
-    const int chunks = (nw + M - 1) / M;
-    const long long nblk = (long long)tiles_u * tiles_v * chunks;
+    const long long nblk = (long long)yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
     const long long grid = (nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), 0, stream, g, k, f, out, jc,
-                       tiles_u, chunks);
+    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), 0, stream, g, k, f, out, jc);
     return hipGetLastError();
+}
+
+int yee_blocks(int nx, int ny) {
+    Geom g{};
+    g.n[0] = nx;
+    g.n[1] = ny;
+    g.n[2] = 1;
+    return yee_tiles<2>(g) * yee_chunks<2>(g);
 }
 
 template <typename real, int DIM>
@@ -791,30 +797,22 @@ hipError_t launch_bin_particles(const Geom& g, const PArrays<real>& p, const Seg
 }
 
 template <typename real>
-hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
-                               const Fields<freal>& f, hipStream_t stream) {
-    hipLaunchKernelGGL((k_fdtd_b_batch<real>), dim3(nblocks), dim3(kFx, kFy), 0, stream, runs, blk_run, f);
-    return hipGetLastError();
-}
-
-template <typename real>
-hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
-                               const Fields<freal>& f, freal* const* jclear, hipStream_t stream) {
+hipError_t launch_yee_fused_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
+                                  const Fields<freal>& f, const Fields<freal>& out, freal* const* jclear,
+                                  hipStream_t stream) {
     JClear jc{{nullptr, nullptr, nullptr}};
     if (jclear)
         for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
-    hipLaunchKernelGGL((k_fdtd_e_batch<real>), dim3(nblocks), dim3(kFx, kFy), 0, stream, runs, blk_run, f, jc);
+    const long long grid = ((long long)nblocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_yee_fused_batch<real>), dim3((unsigned)grid), dim3(kBlock), 0, stream, runs, blk_run,
+                       nblocks, f, out, jc);
     return hipGetLastError();
 }
 
-template hipError_t launch_fdtd_b_batch<float>(const RunDesc<float>*, const int32_t*, int, const Fields<freal>&,
-                                               hipStream_t);
-template hipError_t launch_fdtd_b_batch<double>(const RunDesc<double>*, const int32_t*, int, const Fields<freal>&,
-                                                hipStream_t);
-template hipError_t launch_fdtd_e_batch<float>(const RunDesc<float>*, const int32_t*, int, const Fields<freal>&,
-                                               freal* const*, hipStream_t);
-template hipError_t launch_fdtd_e_batch<double>(const RunDesc<double>*, const int32_t*, int, const Fields<freal>&,
-                                                freal* const*, hipStream_t);
+template hipError_t launch_yee_fused_batch<float>(const RunDesc<float>*, const int32_t*, int, const Fields<freal>&,
+                                                  const Fields<freal>&, freal* const*, hipStream_t);
+template hipError_t launch_yee_fused_batch<double>(const RunDesc<double>*, const int32_t*, int, const Fields<freal>&,
+                                                   const Fields<freal>&, freal* const*, hipStream_t);
 
 template <typename real>
 hipError_t launch_field_energy(const Geom& g, const Fields<real>& f, double* acc,

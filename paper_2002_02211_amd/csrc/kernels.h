@@ -42,7 +42,7 @@ struct RunDesc {
     long long cell_off;
     int sid_base;
     int tile_base;
-    int fdtd_blk_base;   // first block of this run in the field-update launches
+    int yee_blk_base;    // first block of this run in the field-update launch
 };
 
 struct TileRef {
@@ -74,17 +74,15 @@ template <typename real>
 hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p, const Segs& seg,
                                const PArrays<real>& lv, const PArrays<real>& st, int32_t* ctr, int slot,
                                unsigned long long* moved, int blocks, hipStream_t stream);
-// Field update of every run: each run covered by its own 64 x 4-cell
-// blocks, fdtd_blocks(n) of them from runs[r].fdtd_blk_base on; blk_run[b]
-// is the run of block b (nblocks in all).
-constexpr int fdtd_blocks_x(int nx) { return (nx + 63) / 64; }
-constexpr int fdtd_blocks(int nx, int ny) { return fdtd_blocks_x(nx) * ((ny + 3) / 4); }
+// Field update of every run (fused Yee step, periodic): each run covered
+// by its own blocks, yee_blocks(nx, ny) of them from runs[r].yee_blk_base
+// on; blk_run[b] is the run of block b (nblocks in all).  Reads f, writes
+// out (distinct arrays of the same size); zeroes jclear.
+int yee_blocks(int nx, int ny);
 template <typename real>
-hipError_t launch_fdtd_b_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
-                               const Fields<freal>& f, hipStream_t stream);
-template <typename real>
-hipError_t launch_fdtd_e_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
-                               const Fields<freal>& f, freal* const* jclear, hipStream_t stream);
+hipError_t launch_yee_fused_batch(const RunDesc<real>* runs, const int32_t* blk_run, int nblocks,
+                                  const Fields<freal>& f, const Fields<freal>& out, freal* const* jclear,
+                                  hipStream_t stream);
 
 // Moving window.  A shift moves the box S cells along +x: every field array
 // shifts S cells towards -x with zeros in the last S columns (dst must not
