@@ -340,6 +340,7 @@ private:
     // swapped with f_'s
     freal* enext_[3] = {nullptr, nullptr, nullptr};
     freal* bnext_[3] = {nullptr, nullptr, nullptr};
+    freal* mur_next_ = nullptr;   // spare Mur state (open x faces)
     int jcur_ = 0;                 // buffer holding the last step's current
     long long store_cap_ = 0;      // slots of the leaver and overflow stores
     // moving window
@@ -747,25 +748,20 @@ Status Engine<real, DIM>::step(int nsteps) {
         tstop(2);
         if (deposit_) {
             tstart(3);
-            if (!g_.open_x) {
-                // periodic: one fused pass into the spare arrays
-                Fields<freal> nf = f_;
-                for (int a = 0; a < 3; ++a) {
-                    nf.E[a] = enext_[a];
-                    nf.B[a] = bnext_[a];
-                }
-                HIP_OR_FAIL((launch_yee_fused<freal, DIM>(g_, kf_, f_, nf, jbuf_[jcur_], stream_)));
-                for (int a = 0; a < 3; ++a) {
-                    std::swap(f_.E[a], enext_[a]);
-                    std::swap(f_.B[a], bnext_[a]);
-                }
-            } else {
-                // open x faces: the Mur ghosts are advanced between the
-                // three updates, in place
-                HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 0, stream_)));
-                HIP_OR_FAIL((launch_fdtd_e<freal, DIM>(g_, kf_, f_, jbuf_[jcur_], stream_)));
-                HIP_OR_FAIL((launch_fdtd_b<freal, DIM>(g_, kf_, f_, 1, stream_)));
+            // one fused pass into the spare arrays (and, with open x faces,
+            // the advanced Mur state into the spare state)
+            Fields<freal> nf = f_;
+            for (int a = 0; a < 3; ++a) {
+                nf.E[a] = enext_[a];
+                nf.B[a] = bnext_[a];
             }
+            nf.mur = mur_next_;
+            HIP_OR_FAIL((launch_yee_fused<freal, DIM>(g_, kf_, f_, nf, jbuf_[jcur_], stream_)));
+            for (int a = 0; a < 3; ++a) {
+                std::swap(f_.E[a], enext_[a]);
+                std::swap(f_.B[a], bnext_[a]);
+            }
+            if (g_.open_x) std::swap(f_.mur, mur_next_);
             tstop(3);
         }
         // the overflow count for the next check (read only there: a copy
@@ -1267,10 +1263,11 @@ Status Engine<real, DIM>::window(const pic_window_config* w) {
     if (!scratch_) {
         scratch_ = (freal*)dalloc(g_.ncells * sizeof(freal));
         f_.mur = (freal*)dalloc((size_t)MUR_COLUMNS * g_.n[1] * g_.n[2] * sizeof(freal));
+        mur_next_ = (freal*)dalloc((size_t)MUR_COLUMNS * g_.n[1] * g_.n[2] * sizeof(freal));
         seg_tmp_.start = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
         seg_tmp_.cap = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
         seg_tmp_.count = (int32_t*)dalloc((size_t)nseg_ * sizeof(int32_t));
-        if (!scratch_ || !f_.mur || !seg_tmp_.start || !seg_tmp_.cap || !seg_tmp_.count)
+        if (!scratch_ || !f_.mur || !mur_next_ || !seg_tmp_.start || !seg_tmp_.cap || !seg_tmp_.count)
             return fail(PIC_ENOMEM, "device allocation failed");
     }
     {

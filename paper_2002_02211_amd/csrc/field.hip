@@ -5,138 +5,20 @@
 
 namespace spinpic {
 
-constexpr int kFx = 64, kFy = 4;   // field kernels: 64 x 4 threads, x fastest
-
-// B -= (dt/2) curl E.  B_x sits at (i, j+1/2, k+1/2), B_y at (i+1/2, j, k+1/2),
-// B_z at (i+1/2, j+1/2, k); E_a at half a cell along a.  Forward differences
-// with periodic wrap.  In 2D every d/dz is zero.
-template <typename real, int DIM>
-__device__ inline void fdtd_b_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, int i, int j, int kz,
-                                 bool update_hi) {
-    const int nx = g.n[0], ny = g.n[1];
-    const long long nxy = (long long)nx * ny;
-    const long long c = kz * nxy + (long long)j * nx + i;
-    const long long ip = i + 1 == nx ? c - i : c + 1;
-    const long long jp = j + 1 == ny ? c - (long long)j * nx : c + nx;
-    const real* __restrict__ Ex = f.E[0];
-    const real* __restrict__ Ey = f.E[1];
-    const real* __restrict__ Ez = f.E[2];
-    const real ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    // E_y and E_z one cell along +x; beyond an open high x face, the Mur
-    // ghosts, advanced first in the second half step (E then holds the new
-    // step's values): ghost = last(old) + k (last(new) - ghost(old))
-    real eyp, ezp;
-    if (g.open_x && i + 1 == nx) {
-        const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
-        real* m = f.mur + ((long long)kz * g.n[1] + j);
-        real gy = m[MUR_HI_GHOST * nrow], gz = m[(MUR_HI_GHOST + 1) * nrow];
-        if (update_hi) {
-            const real py = m[MUR_HI_PREV * nrow], pz = m[(MUR_HI_PREV + 1) * nrow];
-            gy = py + k.mur_k * (ey - gy);
-            gz = pz + k.mur_k * (ez - gz);
-            m[MUR_HI_GHOST * nrow] = gy;
-            m[(MUR_HI_GHOST + 1) * nrow] = gz;
-            m[MUR_HI_PREV * nrow] = ey;
-            m[(MUR_HI_PREV + 1) * nrow] = ez;
-        }
-        eyp = gy;
-        ezp = gz;
-    } else {
-        eyp = Ey[ip];
-        ezp = Ez[ip];
-    }
-    real cx = k.cb[1] * (Ez[jp] - ez);                 // d/dy E_z
-    real cy = -k.cb[0] * (ezp - ez);                   // -d/dx E_z
-    const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (Ex[jp] - ex);
-    if (DIM == 3) {
-        const long long kp = kz + 1 == g.n[2] ? c - kz * nxy : c + nxy;
-        cx -= k.cb[2] * (Ey[kp] - ey);                 // -d/dz E_y
-        cy += k.cb[2] * (Ex[kp] - ex);                 // d/dz E_x
-    }
-    f.B[0][c] -= cx;
-    f.B[1][c] -= cy;
-    f.B[2][c] -= cz;
-}
-
-template <typename real, int DIM>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_b(Geom g, Consts<real> k, Fields<real> f, int update_hi) {
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    fdtd_b_at<real, DIM>(g, k, f, i, j, blockIdx.z, update_hi != 0);
-}
-
-// E += dt (curl B - J).  Backward differences with periodic wrap.  The
-// other current buffer, no longer needed, is zeroed here for the next
-// step's deposit (when jclear is non-NULL).
+// The current buffer of the previous step, no longer needed, is zeroed by
+// the Yee step for the next step's deposit (when jclear is non-NULL).
 struct JClear {
     void* c[3];
 };
 
-template <typename real, int DIM>
-__device__ inline void fdtd_e_at(const Geom& g, const Consts<real>& k, const Fields<real>& f, const JClear& jclear,
-                                 int i, int j, int kz) {
-    const int nx = g.n[0], ny = g.n[1];
-    const long long nxy = (long long)nx * ny;
-    const long long c = kz * nxy + (long long)j * nx + i;
-    const long long im = i == 0 ? c + nx - 1 : c - 1;
-    const long long jm = j == 0 ? c + (long long)(ny - 1) * nx : c - nx;
-    const real* __restrict__ Bx = f.B[0];
-    const real* __restrict__ By = f.B[1];
-    const real* __restrict__ Bz = f.B[2];
-    const real bx = Bx[c], by = By[c], bz = Bz[c];
-    // B_y and B_z one cell along -x; beyond an open low x face, the Mur
-    // ghosts advanced to this half step: ghost = first(old) + k (first(new)
-    // - ghost(old))
-    real bym, bzm;
-    if (g.open_x && i == 0) {
-        const long long nrow = (long long)g.n[1] * (DIM == 3 ? g.n[2] : 1);
-        real* m = f.mur + ((long long)kz * g.n[1] + j);
-        const real gy = m[MUR_LO_GHOST * nrow], gz = m[(MUR_LO_GHOST + 1) * nrow];
-        const real py = m[MUR_LO_PREV * nrow], pz = m[(MUR_LO_PREV + 1) * nrow];
-        bym = py + k.mur_k * (by - gy);
-        bzm = pz + k.mur_k * (bz - gz);
-        m[MUR_LO_GHOST * nrow] = bym;
-        m[(MUR_LO_GHOST + 1) * nrow] = bzm;
-        m[MUR_LO_PREV * nrow] = by;
-        m[(MUR_LO_PREV + 1) * nrow] = bz;
-    } else {
-        bym = By[im];
-        bzm = Bz[im];
-    }
-    real cx = k.ce[1] * (bz - Bz[jm]);                 // d/dy B_z
-    real cy = -k.ce[0] * (bz - bzm);                   // -d/dx B_z
-    const real cz = k.ce[0] * (by - bym) - k.ce[1] * (bx - Bx[jm]);
-    if (DIM == 3) {
-        const long long km = kz == 0 ? c + (g.n[2] - 1) * nxy : c - nxy;
-        cx -= k.ce[2] * (by - By[km]);                 // -d/dz B_y
-        cy += k.ce[2] * (bx - Bx[km]);                 // d/dz B_x
-    }
-    f.E[0][c] += cx - k.dt * f.J[0][c];
-    f.E[1][c] += cy - k.dt * f.J[1][c];
-    f.E[2][c] += cz - k.dt * f.J[2][c];
-    if (jclear.c[0]) {
-        static_cast<real*>(jclear.c[0])[c] = real(0);
-        static_cast<real*>(jclear.c[1])[c] = real(0);
-        static_cast<real*>(jclear.c[2])[c] = real(0);
-    }
-}
+// ---------------------------------------------------------------- Yee step
 
-template <typename real, int DIM>
-__global__ void __launch_bounds__(kFx * kFy)
-k_fdtd_e(Geom g, Consts<real> k, Fields<real> f, JClear jclear) {
-    const int i = blockIdx.x * kFx + threadIdx.x;
-    const int j = blockIdx.y * kFy + threadIdx.y;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    fdtd_e_at<real, DIM>(g, k, f, jclear, i, j, blockIdx.z);
-}
-
-// ---------------------------------------------------------------- fused Yee step
-
-// The whole Yee step of periodic fields in one pass: B' = B - (dt/2) curl E,
-// E_out = E + dt (curl B' - J), B_out = B' - (dt/2) curl E_out, with the same
-// differences as k_fdtd_b and k_fdtd_e.  The step reads E, B and J once and
+// The Yee step in one pass: B' = B - (dt/2) curl E, E_out = E + dt (curl B'
+// - J), B_out = B' - (dt/2) curl E_out.  B_x sits at (i, j+1/2, k+1/2), B_y
+// at (i+1/2, j, k+1/2), B_z at (i+1/2, j+1/2, k) and E_a half a cell along
+// a, so curl E takes forward and curl B backward differences, with periodic
+// wrap along y and z, and along x unless its faces are open (Mur ghosts,
+// below).  In 2D every d/dz is zero.  The step reads E, B and J once and
 // writes E_out and B_out once (the input arrays are not written: other
 // workgroups still read them as guard cells).
 //
@@ -228,6 +110,42 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
     const bool ownO = t < RX * RY && x0 + ou < nx && (DIM == 2 || y0 + ov < ny);
     const long long offO = inplane(ou, ov);
 
+    // Open x faces (Mur): the B' cells of the last column take E_y, E_z one
+    // cell beyond from the high ghosts as they stand; the E_out cells of the
+    // first column take B'_y, B'_z one cell below from the low ghosts
+    // advanced to this step, and the B_out cells of the last column E_out
+    // from the high ghosts advanced to this step.  The state is read from
+    // f.mur and the advanced state written to out.mur, each row by the one
+    // thread that owns its face cell: ghost(new) = inside(old) + k
+    // (inside(new) - ghost(old)).  Blocks that also compute a neighbour's
+    // face cells (a run's guard planes) advance the ghosts themselves from
+    // the old state, which no block overwrites.
+    const bool open = g.open_x != 0;
+    const long long nrow = (long long)ny * (DIM == 3 ? g.n[2] : 1);
+    auto mrow = [&](int w, int v) -> long long {
+        if (DIM == 3) return (long long)wrap_index(w, nw) * ny + wrap_index(y0 + v, ny);
+        return wrap_index(w, nw);
+    };
+    const bool hiB = open && hasB && x0 - 1 + t % D::BX == nx - 1;
+    const bool loF = open && hasF && x0 + fu == 0;
+    const bool hiO = open && ownO && x0 + ou == nx - 1;
+    // the old state of the block's rows (planes m0 - 1 .. m0 + M, in-plane
+    // rows y0 - 1 .. y0 + RY in 3D) is staged in shared memory first, so
+    // that no global load of it sits in the plane loop
+    constexpr int MY = DIM == 3 ? RY + 2 : 1;
+    __shared__ real sMur[MUR_COLUMNS][M + 2][MY];
+    auto mur_old = [&](int col, int w, int v) -> real {
+        return sMur[col][w - (m0 - 1)][DIM == 3 ? v + 1 : 0];
+    };
+    if (open) {
+        for (int idx = t; idx < MUR_COLUMNS * (M + 2) * MY; idx += kBlock) {
+            const int col = idx / ((M + 2) * MY), rem = idx - col * (M + 2) * MY;
+            const int pl = rem / MY, yr = rem - pl * MY;
+            sMur[col][pl][yr] = f.mur[col * nrow + mrow(m0 - 1 + pl, yr - (DIM == 3 ? 1 : 0))];
+        }
+        __syncthreads();
+    }
+
     // Inputs of plane p (E(p + 1), B(p), J(p)) are loaded two planes ahead
     // into one of two register sets, used by turns (the loop is unrolled by
     // two so that each set keeps its registers).
@@ -262,29 +180,37 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
         }
         load_E(q, p + 2);
         __syncthreads();
-        // B'(p) on the block widened by 1
+        // B'(p) on the block widened by 1.  Each phase takes the values one
+        // cell beyond an open face as arguments.
         if (hasB) {
             const int e = (t / D::BX) * D::EX + t % D::BX;   // same cell in the E tile
-            const real ex = sE[s0][0][e], ey = sE[s0][1][e], ez = sE[s0][2][e];
-            const real eyp = sE[s0][1][e + 1], ezp = sE[s0][2][e + 1];      // +x
-            real ezy, exy;                                                   // +y
-            if (DIM == 3) {
-                ezy = sE[s0][2][e + D::EX];
-                exy = sE[s0][0][e + D::EX];
+            auto bprime = [&](real eyp, real ezp) {          // E_y, E_z one cell along +x
+                const real ex = sE[s0][0][e], ey = sE[s0][1][e], ez = sE[s0][2][e];
+                real ezy, exy;                               // +y
+                if (DIM == 3) {
+                    ezy = sE[s0][2][e + D::EX];
+                    exy = sE[s0][0][e + D::EX];
+                } else {
+                    ezy = sE[s1][2][e];
+                    exy = sE[s1][0][e];
+                }
+                real cx = k.cb[1] * (ezy - ez);
+                real cy = -k.cb[0] * (ezp - ez);
+                const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
+                if (DIM == 3) {
+                    cx -= k.cb[2] * (sE[s1][1][e] - ey);
+                    cy += k.cb[2] * (sE[s1][0][e] - ex);
+                }
+                sB[s0][0][t] = q.B[0] - cx;
+                sB[s0][1][t] = q.B[1] - cy;
+                sB[s0][2][t] = q.B[2] - cz;
+            };
+            if (hiB) {
+                const int v = t / D::BX - 1;
+                bprime(mur_old(MUR_HI_GHOST, p, v), mur_old(MUR_HI_GHOST + 1, p, v));
             } else {
-                ezy = sE[s1][2][e];
-                exy = sE[s1][0][e];
+                bprime(sE[s0][1][e + 1], sE[s0][2][e + 1]);
             }
-            real cx = k.cb[1] * (ezy - ez);
-            real cy = -k.cb[0] * (ezp - ez);
-            const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
-            if (DIM == 3) {
-                cx -= k.cb[2] * (sE[s1][1][e] - ey);
-                cy += k.cb[2] * (sE[s1][0][e] - ex);
-            }
-            sB[s0][0][t] = q.B[0] - cx;
-            sB[s0][1][t] = q.B[1] - cy;
-            sB[s0][2][t] = q.B[2] - cz;
         }
         load_B(q, p + 2);
         __syncthreads();
@@ -294,39 +220,57 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
                 const int r = fv + (DIM == 3 ? 1 : 0);
                 const int bb = r * D::BX + fu + 1;   // same cell in the B' tile
                 const int e = r * D::EX + fu + 1;    // and in the E tile
-                const real bx = sB[s0][0][bb], by = sB[s0][1][bb], bz = sB[s0][2][bb];
-                const real bym = sB[s0][1][bb - 1], bzm = sB[s0][2][bb - 1];   // -x
-                real bzy, bxy;                                                  // -y
-                if (DIM == 3) {
-                    bzy = sB[s0][2][bb - D::BX];
-                    bxy = sB[s0][0][bb - D::BX];
-                } else {
-                    bzy = sB[sm][2][bb];
-                    bxy = sB[sm][0][bb];
-                }
-                real cx = k.ce[1] * (bz - bzy);
-                real cy = -k.ce[0] * (bz - bzm);
-                const real cz = k.ce[0] * (by - bym) - k.ce[1] * (bx - bxy);
-                if (DIM == 3) {
-                    cx -= k.ce[2] * (by - sB[sm][1][bb]);
-                    cy += k.ce[2] * (bx - sB[sm][0][bb]);
-                }
-                const real e0 = sE[s0][0][e] + (cx - k.dt * q.J[0]);
-                const real e1 = sE[s0][1][e] + (cy - k.dt * q.J[1]);
-                const real e2 = sE[s0][2][e] + (cz - k.dt * q.J[2]);
-                sF[s0][0][t] = e0;
-                sF[s0][1][t] = e1;
-                sF[s0][2][t] = e2;
-                if (ownF && p < mend) {
-                    const long long c = plane(p) + offF;
-                    out.E[0][c] = e0;
-                    out.E[1][c] = e1;
-                    out.E[2][c] = e2;
-                    if (jclear.c[0]) {
-                        static_cast<real*>(jclear.c[0])[c] = real(0);
-                        static_cast<real*>(jclear.c[1])[c] = real(0);
-                        static_cast<real*>(jclear.c[2])[c] = real(0);
+                auto eout = [&](real bym, real bzm) {   // B'_y, B'_z one cell along -x
+                    const real bx = sB[s0][0][bb], by = sB[s0][1][bb], bz = sB[s0][2][bb];
+                    real bzy, bxy;                      // -y
+                    if (DIM == 3) {
+                        bzy = sB[s0][2][bb - D::BX];
+                        bxy = sB[s0][0][bb - D::BX];
+                    } else {
+                        bzy = sB[sm][2][bb];
+                        bxy = sB[sm][0][bb];
                     }
+                    real cx = k.ce[1] * (bz - bzy);
+                    real cy = -k.ce[0] * (bz - bzm);
+                    const real cz = k.ce[0] * (by - bym) - k.ce[1] * (bx - bxy);
+                    if (DIM == 3) {
+                        cx -= k.ce[2] * (by - sB[sm][1][bb]);
+                        cy += k.ce[2] * (bx - sB[sm][0][bb]);
+                    }
+                    const real e0 = sE[s0][0][e] + (cx - k.dt * q.J[0]);
+                    const real e1 = sE[s0][1][e] + (cy - k.dt * q.J[1]);
+                    const real e2 = sE[s0][2][e] + (cz - k.dt * q.J[2]);
+                    sF[s0][0][t] = e0;
+                    sF[s0][1][t] = e1;
+                    sF[s0][2][t] = e2;
+                    if (ownF && p < mend) {
+                        const long long c = plane(p) + offF;
+                        out.E[0][c] = e0;
+                        out.E[1][c] = e1;
+                        out.E[2][c] = e2;
+                        if (jclear.c[0]) {
+                            static_cast<real*>(jclear.c[0])[c] = real(0);
+                            static_cast<real*>(jclear.c[1])[c] = real(0);
+                            static_cast<real*>(jclear.c[2])[c] = real(0);
+                        }
+                    }
+                };
+                if (loF) {
+                    const long long mr = mrow(p, fv);
+                    const real by = sB[s0][1][bb], bz = sB[s0][2][bb];
+                    const real gy = mur_old(MUR_LO_GHOST, p, fv), gz = mur_old(MUR_LO_GHOST + 1, p, fv);
+                    const real py = mur_old(MUR_LO_PREV, p, fv), pz = mur_old(MUR_LO_PREV + 1, p, fv);
+                    const real bym = py + k.mur_k * (by - gy);
+                    const real bzm = pz + k.mur_k * (bz - gz);
+                    if (ownF && p < mend) {
+                        out.mur[MUR_LO_GHOST * nrow + mr] = bym;
+                        out.mur[(MUR_LO_GHOST + 1) * nrow + mr] = bzm;
+                        out.mur[MUR_LO_PREV * nrow + mr] = by;
+                        out.mur[(MUR_LO_PREV + 1) * nrow + mr] = bz;
+                    }
+                    eout(bym, bzm);
+                } else {
+                    eout(sB[s0][1][bb - 1], sB[s0][2][bb - 1]);
                 }
             }
             __syncthreads();
@@ -336,27 +280,43 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
             // B_out(p - 1) on the block
             const int fi = ov * D::FX + ou;                                  // E_out tile
             const int bb = (ov + (DIM == 3 ? 1 : 0)) * D::BX + ou + 1;       // B' tile
-            const real ex = sF[sm][0][fi], ey = sF[sm][1][fi], ez = sF[sm][2][fi];
-            const real eyp = sF[sm][1][fi + 1], ezp = sF[sm][2][fi + 1];    // +x
-            real ezy, exy;                                                   // +y
-            if (DIM == 3) {
-                ezy = sF[sm][2][fi + D::FX];
-                exy = sF[sm][0][fi + D::FX];
+            auto bout = [&](real eyp, real ezp) {   // E_out y, z one cell along +x
+                const real ex = sF[sm][0][fi], ey = sF[sm][1][fi], ez = sF[sm][2][fi];
+                real ezy, exy;                      // +y
+                if (DIM == 3) {
+                    ezy = sF[sm][2][fi + D::FX];
+                    exy = sF[sm][0][fi + D::FX];
+                } else {
+                    ezy = sF[s0][2][fi];
+                    exy = sF[s0][0][fi];
+                }
+                real cx = k.cb[1] * (ezy - ez);
+                real cy = -k.cb[0] * (ezp - ez);
+                const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
+                if (DIM == 3) {
+                    cx -= k.cb[2] * (sF[s0][1][fi] - ey);
+                    cy += k.cb[2] * (sF[s0][0][fi] - ex);
+                }
+                const long long c = plane(p - 1) + offO;
+                out.B[0][c] = sB[sm][0][bb] - cx;
+                out.B[1][c] = sB[sm][1][bb] - cy;
+                out.B[2][c] = sB[sm][2][bb] - cz;
+            };
+            if (hiO) {
+                const long long mr = mrow(p - 1, ov);
+                const real ey = sF[sm][1][fi], ez = sF[sm][2][fi];
+                const real gy = mur_old(MUR_HI_GHOST, p - 1, ov), gz = mur_old(MUR_HI_GHOST + 1, p - 1, ov);
+                const real py = mur_old(MUR_HI_PREV, p - 1, ov), pz = mur_old(MUR_HI_PREV + 1, p - 1, ov);
+                const real eyp = py + k.mur_k * (ey - gy);
+                const real ezp = pz + k.mur_k * (ez - gz);
+                out.mur[MUR_HI_GHOST * nrow + mr] = eyp;
+                out.mur[(MUR_HI_GHOST + 1) * nrow + mr] = ezp;
+                out.mur[MUR_HI_PREV * nrow + mr] = ey;
+                out.mur[(MUR_HI_PREV + 1) * nrow + mr] = ez;
+                bout(eyp, ezp);
             } else {
-                ezy = sF[s0][2][fi];
-                exy = sF[s0][0][fi];
+                bout(sF[sm][1][fi + 1], sF[sm][2][fi + 1]);
             }
-            real cx = k.cb[1] * (ezy - ez);
-            real cy = -k.cb[0] * (ezp - ez);
-            const real cz = k.cb[0] * (eyp - ey) - k.cb[1] * (exy - ex);
-            if (DIM == 3) {
-                cx -= k.cb[2] * (sF[s0][1][fi] - ey);
-                cy += k.cb[2] * (sF[s0][0][fi] - ex);
-            }
-            const long long c = plane(p - 1) + offO;
-            out.B[0][c] = sB[sm][0][bb] - cx;
-            out.B[1][c] = sB[sm][1][bb] - cy;
-            out.B[2][c] = sB[sm][2][bb] - cz;
         }
     };
 
@@ -422,7 +382,7 @@ template hipError_t launch_shift_x<double>(const Geom&, const double*, double*, 
 template <typename real>
 __device__ inline Fields<freal> offset_fields(const Fields<freal>& f, long long off) {
     Fields<freal> r;
-    r.mur = nullptr;   // runs of a batch are periodic
+    r.mur = f.mur;   // runs of a batch are periodic: never read
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         r.E[c] = f.E[c] + off;
@@ -703,17 +663,6 @@ k_nonfinite(const real* data, long long n, int32_t* flag) {
 
 // ---------------------------------------------------------------- launchers
 
-static dim3 field_grid(const Geom& g) {
-    return dim3((g.n[0] + kFx - 1) / kFx, (g.n[1] + kFy - 1) / kFy, g.ndim == 3 ? g.n[2] : 1);
-}
-
-template <typename real, int DIM>
-hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f, int update_hi,
-                         hipStream_t stream) {
-    hipLaunchKernelGGL((k_fdtd_b<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f, update_hi);
-    return hipGetLastError();
-}
-
 // Mur state of open x faces from the current fields: every ghost and
 // previous value starts as the first (low face) or last (high face) column.
 template <typename real, int DIM>
@@ -744,7 +693,7 @@ hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t st
 template <typename real, int DIM>
 hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<real>& f, const Fields<real>& out,
                             real* const* jclear, hipStream_t stream) {
-    if (g.open_x) return hipErrorInvalidValue;   // open faces take the three-kernel step
+    if (g.open_x && (!f.mur || !out.mur || f.mur == out.mur)) return hipErrorInvalidValue;
     JClear jc{{nullptr, nullptr, nullptr}};
     if (jclear)
         for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
@@ -760,17 +709,6 @@ int yee_blocks(int nx, int ny) {
     g.n[1] = ny;
     g.n[2] = 1;
     return yee_tiles<2>(g) * yee_chunks<2>(g);
-}
-
-template <typename real, int DIM>
-hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
-                         real* const* jclear, hipStream_t stream) {
-    JClear jc{{nullptr, nullptr, nullptr}};
-    if (jclear)
-        for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
-    hipLaunchKernelGGL((k_fdtd_e<real, DIM>), field_grid(g), dim3(kFx, kFy), 0, stream, g, k, f,
-                       jc);
-    return hipGetLastError();
 }
 
 template <typename real, int DIM>
@@ -844,15 +782,10 @@ hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStr
 }
 
 #define SPINPIC_INST_GRID(DIM)                                                                 \
-    template hipError_t launch_fdtd_b<double, DIM>(const Geom&, const Consts<double>&,        \
-                                                   const Fields<double>&, int, hipStream_t);   \
     template hipError_t launch_yee_fused<double, DIM>(const Geom&, const Consts<double>&,     \
         const Fields<double>&, const Fields<double>&, double* const*, hipStream_t);             \
     template hipError_t launch_mur_reset<double, DIM>(const Geom&, const Fields<double>&,     \
                                                       hipStream_t);                            \
-    template hipError_t launch_fdtd_e<double, DIM>(const Geom&, const Consts<double>&,        \
-                                                   const Fields<double>&, double* const*,      \
-                                                   hipStream_t);                               \
     template hipError_t launch_div_residual<double, DIM>(const Geom&, const Vec3d&,           \
         const Fields<double>&, const double*, const double*, double*, double*, int, hipStream_t);
 

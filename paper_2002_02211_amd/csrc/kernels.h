@@ -114,26 +114,18 @@ template <typename real, int DIM>
 hipError_t launch_inject(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
                          int32_t* ctr, const InjectArgs& a, hipStream_t stream);
 
-// Yee update: B -= (dt/2) curl E, or E += dt (curl B - J) while zeroing the
-// three current arrays jclear (may be NULL).
-// update_hi: the second B half step of a step, which first advances the
-// Mur ghosts of an open high x face (E holds the new step's values).
-template <typename real, int DIM>
-hipError_t launch_fdtd_b(const Geom& g, const Consts<real>& k, const Fields<real>& f, int update_hi,
-                         hipStream_t stream);
-// The whole Yee step (B half step, E step with -dt J, B half step) of
-// periodic fields in one pass: reads f.E, f.B, f.J, writes out.E and out.B
-// (distinct arrays of the same size); zeroes jclear like launch_fdtd_e.
-// Returns hipErrorInvalidValue for open x faces.
+// The whole Yee step (B half step, E step with -dt J, B half step) in one
+// pass: reads f.E, f.B, f.J, writes out.E and out.B (distinct arrays of the
+// same size) and zeroes the three current arrays jclear (may be NULL).
+// With open x faces (g.open_x) it reads the Mur state from f.mur and writes
+// the advanced state to out.mur (distinct, MUR_COLUMNS x ny nz values each);
+// hipErrorInvalidValue if either is missing.
 template <typename real, int DIM>
 hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<real>& f, const Fields<real>& out,
                             real* const* jclear, hipStream_t stream);
 // Mur state of open x faces (f.mur) started from the current fields.
 template <typename real, int DIM>
 hipError_t launch_mur_reset(const Geom& g, const Fields<real>& f, hipStream_t stream);
-template <typename real, int DIM>
-hipError_t launch_fdtd_e(const Geom& g, const Consts<real>& k, const Fields<real>& f,
-                         real* const* jclear, hipStream_t stream);
 
 // FP64 reductions.  acc receives sums by atomic adds and must be zeroed first.
 //   polarization: acc[0..2] += s, acc[3] += 1 over the selected particles.
