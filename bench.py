@@ -79,11 +79,21 @@ def algorithmic_bytes(ndim, precision, npart, ncells):
 BREAKDOWN_STEPS = 20   # steps after the timed ones, with events around every kernel
 
 
+def _code_only(text):
+    """C++ source without comments and blank space, so that the hash below
+    changes with the code only."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash():
+    """Hash of the library's kernel and driver sources (code only)."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_2002_02211_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

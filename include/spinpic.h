@@ -251,8 +251,7 @@ int pic_window(pic_ctx* ctx, const pic_window_config* w);
  * pic_timing_read fills ms_out[k] (total milliseconds) and launches_out[k]
  * for k = 0 push+deposit (including the compaction of the slots tile
  * leavers vacate), 1 overflow push, 2 insertion of tile leavers, 3 field
- * update (the fused Yee pass, or its three kernels with open x faces);
- * cap >= 4.  Waits. */
+ * update (one fused Yee pass per step); cap >= 4.  Waits. */
 int pic_timing(pic_ctx* ctx, int32_t enable);
 int pic_timing_read(pic_ctx* ctx, double* ms_out, int64_t* launches_out, int32_t cap);
 
@@ -270,7 +269,7 @@ void pic_free(pic_ctx* ctx);
  * The runs share one particle store and concatenated field arrays; a step is
  * one persistent push over the tiles of every run (largest tiles first, the
  * workgroups taking tiles from a queue until none is left), one overflow
- * push, one leaver insertion and three field-update launches, whatever the
+ * push, one leaver insertion and one field-update launch, whatever the
  * number of runs.  Each run is the step of pic_step on its own grid.
  * ------------------------------------------------------------------------- */
 typedef struct pic_batch pic_batch;

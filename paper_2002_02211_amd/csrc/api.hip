@@ -1376,8 +1376,8 @@ Status Engine<real, DIM>::timing_read(double* ms, int64_t* launches, int cap) {
 // Independent 2D runs of uneven size in shared stores: one segment list, one
 // particle store and concatenated field arrays, each run at its own offsets.
 // A step is one persistent push over all runs' tiles (largest first), one
-// overflow push, one leaver insertion and the three field-update launches
-// over all runs at once.
+// overflow push, one leaver insertion and one fused Yee pass over all runs
+// at once.
 class BatchBase {
 public:
     virtual ~BatchBase() {}
