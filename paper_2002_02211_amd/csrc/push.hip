@@ -525,6 +525,28 @@ k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict
         push_stash_one<real, DIM>(g, k, st, i, st.sp[i], f, deposit);
 }
 
+// Positions for the active lanes of a wavefront that each add 1 to
+// counter[key]: one atomic add per distinct key among them (the leavers of
+// a wavefront mostly come from one tile and go to a few neighbours), each
+// lane's position being the group's old count plus its rank in the group.
+// Every lane of the wavefront must call it.
+__device__ inline int wave_reserve(int32_t* counter, int key, bool active) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    int pos = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lkey = __shfl(key, leader);
+        const unsigned long long grp = __ballot(active && key == lkey) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counter[lkey], __popcll(grp));
+        base = __shfl(base, leader);
+        if ((grp >> lane) & 1ull) pos = base + __popcll(grp & ((1ull << lane) - 1ull));
+        pending &= ~grp;
+    }
+    return pos;
+}
+
 // Every leaver takes a slot at the end of its new segment, or a slot in the
 // overflow store when the segment is full.
 template <typename real, int DIM>
@@ -533,15 +555,24 @@ k_insert(Geom g, PArrays<real> p, Segs seg, PArrays<real> lv, PArrays<real> st,
          int32_t* __restrict__ ctr, int slot, unsigned long long* __restrict__ moved) {
     const int L = ctr[slot];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(moved, (unsigned long long)L);
-    for (int q = blockIdx.x * kBlock + threadIdx.x; q < L; q += gridDim.x * kBlock) {
-        const int32_t cell = lv.cell[q];
-        if (cell == kDeadCell) continue;   // left the box: dropped
-        int c[3];
-        unpack_cell<DIM>(cell, c[0], c[1], c[2]);
-        const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1] + (DIM == 3 ? g.nt[1] * (c[2] / g.T[2]) : 0));
-        const int sp = lv.sp[q];
-        const int sid = tile * g.nsp + sp;
-        const int pos = atomicAdd(&seg.count[sid], 1);
+    for (int q0 = blockIdx.x * kBlock; q0 < L; q0 += gridDim.x * kBlock) {
+        const int q = q0 + threadIdx.x;
+        int32_t cell = kDeadCell;
+        int sp = 0, sid = 0;
+        if (q < L) {
+            cell = lv.cell[q];
+            sp = lv.sp[q];
+        }
+        const bool live = cell != kDeadCell;   // a dead leaver left the box: dropped
+        if (live) {
+            int c[3];
+            unpack_cell<DIM>(cell, c[0], c[1], c[2]);
+            const int tile =
+                c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1] + (DIM == 3 ? g.nt[1] * (c[2] / g.T[2]) : 0));
+            sid = tile * g.nsp + sp;
+        }
+        const int pos = wave_reserve(seg.count, sid, live);
+        if (!live) continue;
         if (pos < seg.cap[sid]) {
             copy_particle(lv, q, p, (long long)seg.start[sid] + pos, DIM);
         } else {
@@ -654,16 +685,22 @@ k_insert_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> p, Segs seg
                PArrays<real> st, int32_t* __restrict__ ctr, int slot, unsigned long long* __restrict__ moved) {
     const int L = ctr[slot];
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(moved, (unsigned long long)L);
-    for (int q = blockIdx.x * kBlock + threadIdx.x; q < L; q += gridDim.x * kBlock) {
-        const int tag = lv.sp[q];
-        const int run = tag / kMaxSpecies;
-        const int sp = tag - run * kMaxSpecies;
-        const Geom g = runs[run].g;
-        int c[3];
-        unpack_cell<2>(lv.cell[q], c[0], c[1], c[2]);
-        const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1]);
-        const int sid = runs[run].sid_base + tile * g.nsp + sp;
-        const int pos = atomicAdd(&seg.count[sid], 1);
+    for (int q0 = blockIdx.x * kBlock; q0 < L; q0 += gridDim.x * kBlock) {
+        const int q = q0 + threadIdx.x;
+        const bool live = q < L;
+        int tag = 0, sid = 0;
+        if (live) {
+            tag = lv.sp[q];
+            const int run = tag / kMaxSpecies;
+            const int sp = tag - run * kMaxSpecies;
+            const Geom& g = runs[run].g;
+            int c[3];
+            unpack_cell<2>(lv.cell[q], c[0], c[1], c[2]);
+            const int tile = c[0] / g.T[0] + g.nt[0] * (c[1] / g.T[1]);
+            sid = runs[run].sid_base + tile * g.nsp + sp;
+        }
+        const int pos = wave_reserve(seg.count, sid, live);
+        if (!live) continue;
         if (pos < seg.cap[sid]) {
             copy_particle(lv, q, p, (long long)seg.start[sid] + pos, 2);
         } else {
