@@ -24,7 +24,6 @@ unchanged.  Each counter is scaled by what it reads for the 1 GiB probe
 """
 
 import argparse
-import glob
 import hashlib
 import json
 import math
@@ -88,11 +87,14 @@ def _code_only(text):
     return " ".join(text.split())
 
 
+PUSH_SOURCES = ("push.hip", "common.h", "kernels.h")   # what the push kernels are compiled from
+
+
 def source_hash():
-    """Hash of the library's kernel and driver sources (code only)."""
+    """Hash of the push kernels' sources (code only)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2002_02211_amd", "csrc", "*"))):
-        with open(p, encoding="utf-8") as f:
+    for name in PUSH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2002_02211_amd", "csrc", name), encoding="utf-8") as f:
             h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 

@@ -157,15 +157,22 @@ struct Timer {
 };
 
 // HIP events around each kernel class on a stream: start/stop pairs recorded
-// while on, summed per class by timer_read.
+// while on, summed per class by timer_read.  The events are created ahead,
+// at enable (creating them between launches would delay the launches that
+// follow a wait).
+constexpr size_t kTimerPool = 1024;
+
+void timer_grow(Timer& tm, size_t want) {
+    while (tm.pool.size() < want) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        tm.pool.push_back(e);
+    }
+}
+
 void timer_start(Timer& tm, hipStream_t stream, int k) {
     if (!tm.on || !((tm.mask >> k) & 1u)) return;
-    if (tm.used + 2 > tm.pool.size()) {
-        for (int i = 0; i < 64; ++i) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) == hipSuccess) tm.pool.push_back(e);
-        }
-    }
+    if (tm.used + 2 > tm.pool.size()) timer_grow(tm, 2 * tm.pool.size() + 2);
     if (tm.used + 2 > tm.pool.size()) return;
     hipEvent_t a = tm.pool[tm.used++];
     hipEvent_t b = tm.pool[tm.used++];
@@ -185,6 +192,7 @@ Status timer_enable(Timer& tm, hipStream_t stream, int enable) {
     tm.mask = enable == 2 ? 1u : (1u << kTimers) - 1u;
     tm.rec.clear();
     tm.used = 0;
+    if (tm.on) timer_grow(tm, kTimerPool);
     return Status{};
 }
 
