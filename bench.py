@@ -466,10 +466,10 @@ def window_kw(spec, shift_cells):
                 ramp_len=pl["ramp_len"] if pl["profile"] == "ramp" else 0.0, s0=pl["s0"])
 
 
-def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None, window=False):
+def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None, window=False, slack=0.0):
     """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
     import torch
-    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile)
+    cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile, slack=slack)
     t0 = time.time()
     sim = S.Simulation(cfg, state["particles"], state["fields"])
     if window:
@@ -510,6 +510,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--deposit-acc", default="default", choices=("default", "fp32", "fp64"),
                     help="precision of the per-tile shared-memory current sums (FP32 path)")
+    ap.add_argument("--slack", type=float, default=0.0,
+                    help="spare slots per tile segment as a fraction of its particles (0: the library's default)")
     ap.add_argument("--tile", default=None,
                     help="tile shape in cells, e.g. 16,16 or 8,8,6 (default: the library's choice)")
     ap.add_argument("--diagnostics", action="store_true",
@@ -583,7 +585,7 @@ def main():
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps, tile,
-                                        window=args.window)
+                                        window=args.window, slack=args.slack)
     stats = sim.stats()
     if args.window:
         npart = stats["particles"]   # injected minus removed since the start
@@ -626,6 +628,8 @@ def main():
                      "avg_launch_ms": avg_push_s * 1e3,
                      "push_pushes_per_s": npart / avg_push_s},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
+        "store": {"overflow_particles": stats["overflow"], "repacks": stats["repacks"],
+                  "after_steps": args.warmup + args.steps + BREAKDOWN_STEPS},
     }
     if args.diagnostics:
         result["diagnostics"] = time_diagnostics(sim, spec, npart, precision)
@@ -635,7 +639,7 @@ def main():
 
     if precision == "fp32" and not args.no_fp64_compare:
         sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile,
-                                       window=args.window)
+                                       window=args.window, slack=args.slack)
         P64, _ = sim64.polarization()
         sim64.close()
         del sim64

@@ -1,10 +1,11 @@
-"""The fused Yee step (one pass over E, B and J per step, periodic faces) on
-grids whose blocks and runs of planes end ragged: 2D with 300 columns (one
-block of 253 and a short one) and 21 rows (runs of 8 planes: 8, 8, 5), 3D
-with 40 x 20 x 36 cells (in-plane blocks of 32 x 4: a short column block;
-runs of 16 planes: 16, 16, 4).  Fields and particles must match the FP64
-oracle to 1e-9 after a few steps with the plasma's currents, and the
-fields of a plasma-free run with random initial fields to 1e-12.
+"""The fused Yee step (one pass over E, B and J per step) on grids whose
+blocks and runs of planes end ragged: 2D with 300 columns (one block of 253
+and a short one) and 21 rows (runs of 8 planes: 8, 8, 5), 3D with 40 x 20 x
+36 cells (in-plane blocks of 32 x 4: a short column block; runs of 16
+planes: 16, 16, 4).  Fields and particles must match the FP64 oracle to
+1e-9 after a few steps with the plasma's currents, and the fields of a
+plasma-free run with random initial fields to 1e-12, with periodic faces
+and with open x faces (Mur ghosts).
 """
 
 import numpy as np
@@ -71,6 +72,32 @@ def test_yee_step_vacuum_random_fields(name, preset, n):
     ref = oracle.Sim(spec, {"particles": empty, "fields": fields})
     sim.step(3)
     ref.step(3)
+    F = sim.fields()
+    Fo = ref.fields()
+    for i, nm in enumerate(S.FIELD_NAMES[:6]):
+        e = field_error(F[nm], Fo[i])
+        assert e <= 1e-12, (name, nm, e)
+    sim.close()
+
+
+@pytest.mark.parametrize("name,preset,n", GRIDS, ids=[g[0] for g in GRIDS])
+def test_yee_step_open_faces_random_fields(name, preset, n):
+    """Open x faces (a window that does not move) on the same ragged grids:
+    the Mur ghosts of the first and last columns, advanced inside the one
+    pass, against the oracle's face by face update."""
+    spec = _spec(preset, n)
+    shape = (6, n[2], n[1], n[0])
+    rng = np.random.default_rng(7)
+    fields = rng.standard_normal(shape)
+    empty = [np.zeros((0, 10)) for _ in spec["species"]]
+    _say("fused Yee with open x faces", name, n)
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp64"), empty, fields)
+    win = dict(speed=0.0, shift_cells=sim.stats()["tile"][0], ppc=0, n0=0.0, ramp_start=0.0, ramp_len=0.0,
+               s0=(0.0, 1.0, 0.0))
+    sim.window(**win)
+    ref = oracle.Sim(spec, {"particles": empty, "fields": fields}, window=win)
+    sim.step(5)
+    ref.step(5)
     F = sim.fields()
     Fo = ref.fields()
     for i, nm in enumerate(S.FIELD_NAMES[:6]):
