@@ -50,6 +50,12 @@ struct YeeDims {
     static constexpr int NE = EX * EY, NB = BX * BY, NF = FX * FY;
 };
 
+// Shared memory for the old Mur state of a block's rows and planes.
+template <typename real, int DIM>
+constexpr size_t yee_mur_lds_bytes() {
+    return (size_t)MUR_COLUMNS * (YeeBlock<DIM>::M + 2) * (DIM == 3 ? YeeBlock<DIM>::RY + 2 : 1) * sizeof(real);
+}
+
 // Blocks of one grid: in-plane blocks across, runs of planes down.
 template <int DIM>
 __host__ __device__ inline int yee_tiles_u(const Geom& g) { return (g.n[0] + YeeBlock<DIM>::RX - 1) / YeeBlock<DIM>::RX; }
@@ -132,16 +138,18 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
     // the old state of the block's rows (planes m0 - 1 .. m0 + M, in-plane
     // rows y0 - 1 .. y0 + RY in 3D) is staged in shared memory first, so
     // that no global load of it sits in the plane loop
+    // (dynamic shared memory, launched with its size only for open faces)
     constexpr int MY = DIM == 3 ? RY + 2 : 1;
-    __shared__ real sMur[MUR_COLUMNS][M + 2][MY];
+    extern __shared__ __align__(16) unsigned char yee_dyn[];
+    real* sMur = reinterpret_cast<real*>(yee_dyn);
     auto mur_old = [&](int col, int w, int v) -> real {
-        return sMur[col][w - (m0 - 1)][DIM == 3 ? v + 1 : 0];
+        return sMur[(col * (M + 2) + w - (m0 - 1)) * MY + (DIM == 3 ? v + 1 : 0)];
     };
     if (open) {
         for (int idx = t; idx < MUR_COLUMNS * (M + 2) * MY; idx += kBlock) {
             const int col = idx / ((M + 2) * MY), rem = idx - col * (M + 2) * MY;
             const int pl = rem / MY, yr = rem - pl * MY;
-            sMur[col][pl][yr] = f.mur[col * nrow + mrow(m0 - 1 + pl, yr - (DIM == 3 ? 1 : 0))];
+            sMur[idx] = f.mur[col * nrow + mrow(m0 - 1 + pl, yr - (DIM == 3 ? 1 : 0))];
         }
         __syncthreads();
     }
@@ -699,7 +707,9 @@ hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<r
         for (int a = 0; a < 3; ++a) jc.c[a] = jclear[a];
     const long long nblk = (long long)yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
     const long long grid = (nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), 0, stream, g, k, f, out, jc);
+    const size_t mur_lds = g.open_x ? yee_mur_lds_bytes<real, DIM>() : 0;
+    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), mur_lds, stream, g, k, f, out,
+                       jc);
     return hipGetLastError();
 }
 
