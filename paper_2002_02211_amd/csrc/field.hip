@@ -155,8 +155,8 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
     }
 
     // Inputs of plane p (E(p + 1), B(p), J(p)) are loaded two planes ahead
-    // into one of two register sets, used by turns (the loop is unrolled by
-    // two so that each set keeps its registers).
+    // into one of two register sets, used by turns (the plane loop below is
+    // unrolled, so each set keeps its registers).
     struct PlaneIn {
         real E[3], B[3], J[3];
     };
