@@ -32,13 +32,17 @@ struct JClear {
 // by 1 on both sides, E_out by 1 above.
 template <int DIM>
 struct YeeBlock;
+// 2D: 253 columns, so that the E tile with its guards is one row of 256
+// cells, one per thread.  3D: 32 x 8 cells (an E tile of 35 x 11) on 512
+// threads: against 32 x 4 on 256 threads it fetches a third fewer guard
+// cells again (the 3D field update of c3 1.21 -> 1.10 ms).
 template <>
 struct YeeBlock<2> {
-    static constexpr int RX = 253, RY = 1, M = 8;
+    static constexpr int RX = 253, RY = 1, M = 8, threads = 256;
 };
 template <>
 struct YeeBlock<3> {
-    static constexpr int RX = 32, RY = 4, M = 16;
+    static constexpr int RX = 32, RY = 8, M = 16, threads = 512;
 };
 
 template <int DIM>
@@ -77,7 +81,7 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
                                                                const JClear& jclear, int b) {
     using D = YeeDims<DIM>;
     constexpr int RX = D::RX, RY = D::RY, M = YeeBlock<DIM>::M;
-    static_assert(D::NE <= kBlock, "one E cell per thread");
+    static_assert(D::NE <= YeeBlock<DIM>::threads, "one E cell per thread");
     __shared__ real sE[2][3][D::NE];
     __shared__ real sB[2][3][D::NB];
     __shared__ real sF[2][3][D::NF];
@@ -146,7 +150,7 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
         return sMur[(col * (M + 2) + w - (m0 - 1)) * MY + (DIM == 3 ? v + 1 : 0)];
     };
     if (open) {
-        for (int idx = t; idx < MUR_COLUMNS * (M + 2) * MY; idx += kBlock) {
+        for (int idx = t; idx < MUR_COLUMNS * (M + 2) * MY; idx += YeeBlock<DIM>::threads) {
             const int col = idx / ((M + 2) * MY), rem = idx - col * (M + 2) * MY;
             const int pl = rem / MY, yr = rem - pl * MY;
             sMur[idx] = f.mur[col * nrow + mrow(m0 - 1 + pl, yr - (DIM == 3 ? 1 : 0))];
@@ -356,7 +360,7 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
 // over the 8 XCDs), so the blocks that run side by side are in-plane
 // neighbours whose guard cells meet in that XCD's L2.
 template <typename real, int DIM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(YeeBlock<DIM>::threads)
 k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jclear) {
     const int nblk = yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
     const int per = (nblk + 7) >> 3;
@@ -406,6 +410,7 @@ template <typename real>
 __global__ void __launch_bounds__(kBlock)
 k_yee_fused_batch(const RunDesc<real>* __restrict__ runs, const int32_t* __restrict__ blk_run, int nblk,
                   Fields<freal> f, Fields<freal> out, JClear jclear) {
+    static_assert(YeeBlock<2>::threads == kBlock, "batched 2D Yee blocks are launched with kBlock threads");
     const int per = (nblk + 7) >> 3;
     const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (b >= nblk) return;
@@ -708,7 +713,7 @@ hipError_t launch_yee_fused(const Geom& g, const Consts<real>& k, const Fields<r
     const long long nblk = (long long)yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
     const long long grid = (nblk + 7) / 8 * 8;
     const size_t mur_lds = g.open_x ? yee_mur_lds_bytes<real, DIM>() : 0;
-    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(kBlock), mur_lds, stream, g, k, f, out,
+    hipLaunchKernelGGL((k_yee_fused<real, DIM>), dim3((unsigned)grid), dim3(YeeBlock<DIM>::threads), mur_lds, stream, g, k, f, out,
                        jc);
     return hipGetLastError();
 }

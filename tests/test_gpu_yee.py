@@ -1,8 +1,8 @@
 """The fused Yee step (one pass over E, B and J per step) on grids whose
 blocks and runs of planes end ragged: 2D with 300 columns (one block of 253
 and a short one) and 21 rows (runs of 8 planes: 8, 8, 5), 3D with 40 x 20 x
-36 cells (in-plane blocks of 32 x 4: a short column block; runs of 16
-planes: 16, 16, 4).  Fields and particles must match the FP64 oracle to
+36 cells (in-plane blocks of 32 x 8: short in x and in y; runs of 16 planes:
+16, 16, 4).  Fields and particles must match the FP64 oracle to
 1e-9 after a few steps with the plasma's currents, and the fields of a
 plasma-free run with random initial fields to 1e-12, with periodic faces
 and with open x faces (Mur ghosts).
