@@ -356,15 +356,17 @@ __device__ __attribute__((always_inline)) void yee_fused_block(const Geom& g, co
     }
 }
 
-// Consecutive block numbers go to one XCD (workgroups are dealt round-robin
-// over the 8 XCDs), so the blocks that run side by side are in-plane
-// neighbours whose guard cells meet in that XCD's L2.
+// In 2D consecutive block numbers go to one XCD (workgroups are dealt
+// round-robin over the 8 XCDs), so the blocks that run side by side are
+// in-plane neighbours whose guard cells meet in that XCD's L2.
 template <typename real, int DIM>
 __global__ void __launch_bounds__(YeeBlock<DIM>::threads)
 k_yee_fused(Geom g, Consts<real> k, Fields<real> f, Fields<real> out, JClear jclear) {
     const int nblk = yee_tiles<DIM>(g) * yee_chunks<DIM>(g);
     const int per = (nblk + 7) >> 3;
-    const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // 3D: blocks in launch order (one band across the XCDs measured faster
+    // than a contiguous range per XCD: c3 1.11 -> 1.03 ms; 2D the reverse)
+    const int b = DIM == 3 ? (int)blockIdx.x : (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (b >= nblk) return;
     yee_fused_block<real, DIM>(g, k, f, out, jclear, b);
 }

@@ -425,10 +425,11 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
              int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
     // the other step's leaver counter is free again: clear it for the next step
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
-    // consecutive tiles go to the same XCD (workgroups are dealt round-robin
-    // over the 8 XCDs), so neighbours share guard cells in one L2
-    const int per = (g.ntiles + 7) >> 3;
-    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    // tiles in launch order: workgroups are dealt round-robin over the 8
+    // XCDs, so the tiles running at any time form one contiguous band of
+    // the grid (its guard cells shared through the last-level cache);
+    // giving each XCD a contiguous range of its own measured slower
+    const int t = (int)blockIdx.x;
     if (t >= g.ntiles) return;
     push_tile<real, acc_t, DIM>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0);
 }
