@@ -159,6 +159,20 @@ int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles
 int pic_spectrum(pic_ctx* ctx, int32_t species, double emin, double emax, int32_t nbins,
                  double* count_out, double* weight_out, double* spin_out);
 
+/* pic_spectrum without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the bins are summed in a buffer the library holds
+ * in static device memory, one per GPU (5 * PIC_MAX_SPECTRUM_BINS doubles,
+ * 40 KiB, kept until the process ends), cleared by a kernel at the start of
+ * every call and copied straight into the caller's arrays.  No hipMalloc,
+ * hipFree, allocator callback or host allocation happens on this path.
+ * Same arguments, results and errors as pic_spectrum; nbins above
+ * PIC_MAX_SPECTRUM_BINS is PIC_EINVAL.  Calls that overlap on one GPU (from
+ * several host threads, or on several streams) share the buffer and race:
+ * keep them in sequence.  Waits for the stream. */
+int pic_spectrum_noalloc(pic_ctx* ctx, int32_t species, double emin, double emax, int32_t nbins,
+                         double* count_out, double* weight_out, double* spin_out);
+
 /* Weighted position-momentum histogram of one species: position along axis
  * (0 .. ndim-1, in c/omega0, as pic_particles reports it) in nx bins over
  * [xmin, xmax), momentum mu*u_comp (comp 0 .. 2, in m_e c) in np bins over

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,9 +17,20 @@
 
 using namespace spinpic;
 
+// The bins of pic_spectrum_noalloc (count, weight sum and three spin sums per
+// bin, at most PIC_MAX_SPECTRUM_BINS bins: 40 KiB), one copy on every GPU the
+// library runs on, held until the process ends.  In host code this name is a
+// host-side stand-in, not a device address: host code uses only the address
+// that hipGetSymbolAddress returns for the device (scratch_address below).
+static __device__ __align__(256) double scratch[5 * PIC_MAX_SPECTRUM_BINS];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
 
 struct Status {
     int code = PIC_OK;
@@ -42,6 +54,22 @@ Status fail(int code, const char* fmt, ...) {
         hipError_t _e = (expr);                                                            \
         if (_e != hipSuccess) return fail(PIC_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
     } while (0)
+
+// Device address of `scratch` on device dev, which must be the current
+// device: looked up once per device (at the first pic_init on it) and kept.
+Status scratch_address(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PIC_EINVAL, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return Status{};
+}
 
 // ---------------------------------------------------------------- config
 
@@ -231,6 +259,8 @@ public:
     virtual Status particles(int species, double* out, size_t cap, int64_t* n) = 0;
     virtual Status spectrum(int species, double emin, double emax, int nbins, double* count,
                             double* weight, double* spin) = 0;
+    virtual Status spectrum_noalloc(int species, double emin, double emax, int nbins, double* count,
+                                    double* weight, double* spin) = 0;
     virtual Status phase_space(int species, int axis, double xmin, double xmax, int nx, int comp,
                                double pmin, double pmax, int np, double* out) = 0;
     virtual Status density(int species, double* out, size_t cap) = 0;
@@ -260,6 +290,8 @@ public:
     Status particles(int species, double* out, size_t cap, int64_t* n) override;
     Status spectrum(int species, double emin, double emax, int nbins, double* count, double* weight,
                     double* spin) override;
+    Status spectrum_noalloc(int species, double emin, double emax, int nbins, double* count, double* weight,
+                            double* spin) override;
     Status phase_space(int species, int axis, double xmin, double xmax, int nx, int comp, double pmin,
                        double pmax, int np, double* out) override;
     Status density(int species, double* out, size_t cap) override;
@@ -303,6 +335,8 @@ private:
         return Status{};
     }
     Status reduce(int mode, const ReduceArgs& ra, double* host_acc);
+    Status spectrum_args(int species, double emin, double emax, int nbins, const double* count,
+                         const double* weight, const double* spin, BinArgs& ba);
     Status compute_rho();
     Status residual_max(double* out);
     void tstart(int k);
@@ -343,6 +377,8 @@ private:
     double* blockmax_ = nullptr;
     int resid_blocks_ = 0;
     int32_t* nf_flag_ = nullptr;
+    int dev_ = 0;                  // the device current at init
+    double* spec_buf_ = nullptr;   // this device's static spectrum buffer (scratch)
     freal* jbuf_[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     // the fused Yee step writes the new E and B here; the pointers are then
     // swapped with f_'s
@@ -589,7 +625,12 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         if (L.code) return L;
     }
 
-    // ---- device allocations
+    // ---- device allocations (and this device's static spectrum buffer)
+    HIP_OR_FAIL(hipGetDevice(&dev_));
+    {
+        Status A = scratch_address(dev_, &spec_buf_);
+        if (A.code) return A;
+    }
     Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
     if (S.code) return S;
     store_cap_ = std::max(npart_, 1LL);
@@ -911,21 +952,30 @@ Status Engine<real, DIM>::polarization(int species, double emin, double emax, do
 }
 
 template <typename real, int DIM>
-Status Engine<real, DIM>::spectrum(int species, double emin, double emax, int nbins, double* count,
-                                   double* weight, double* spin) {
+Status Engine<real, DIM>::spectrum_args(int species, double emin, double emax, int nbins, const double* count,
+                                        const double* weight, const double* spin, BinArgs& ba) {
     if (species < -1 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
     if (nbins < 1 || nbins > PIC_MAX_SPECTRUM_BINS)
         return fail(PIC_EINVAL, "nbins = %d outside 1..%d", nbins, PIC_MAX_SPECTRUM_BINS);
     if (!std::isfinite(emin) || !std::isfinite(emax) || !(emin < emax))
         return fail(PIC_EINVAL, "energy range must be finite with emin < emax");
     if (!count || !weight || !spin) return fail(PIC_EINVAL, "output arrays must not be NULL");
-    BinArgs ba{};
+    ba = BinArgs{};
     ba.mode = BIN_SPECTRUM;
     ba.species = species;
     ba.lo = emin;
     ba.hi = emax;
     ba.nbins = nbins;
     for (int sp = 0; sp < kMaxSpecies; ++sp) ba.mu[sp] = sp < g_.nsp ? R_.cfg.sp[sp].mu : 1.0;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::spectrum(int species, double emin, double emax, int nbins, double* count,
+                                   double* weight, double* spin) {
+    BinArgs ba;
+    Status A = spectrum_args(species, emin, emax, nbins, count, weight, spin, ba);
+    if (A.code) return A;
     const size_t nh = (size_t)5 * nbins;
     double* d = (double*)dalloc(nh * sizeof(double));
     if (!d) return fail(PIC_ENOMEM, "spectrum buffer allocation failed");
@@ -941,6 +991,28 @@ Status Engine<real, DIM>::spectrum(int species, double emin, double emax, int nb
         weight[b] = h[nbins + b];
     }
     for (int q = 0; q < 3 * nbins; ++q) spin[q] = h[2 * (size_t)nbins + q];
+    return Status{};
+}
+
+// The same bins summed in the library's static device buffer of this GPU
+// (spec_buf_, 5 * PIC_MAX_SPECTRUM_BINS doubles) and copied straight into the
+// caller's arrays: no device or host allocation.  The buffer is cleared by a
+// kernel first; calls that overlap on one GPU would share it.
+template <typename real, int DIM>
+Status Engine<real, DIM>::spectrum_noalloc(int species, double emin, double emax, int nbins, double* count,
+                                           double* weight, double* spin) {
+    BinArgs ba;
+    Status A = spectrum_args(species, emin, emax, nbins, count, weight, spin, ba);
+    if (A.code) return A;
+    if (!spec_buf_) return fail(PIC_ESTATE, "the static spectrum buffer of device %d was not found", dev_);
+    const size_t nb = (size_t)nbins * sizeof(double);
+    hipError_t e = launch_fill_zero(spec_buf_, 5LL * nbins, stream_);
+    if (e == hipSuccess) e = launch_bin_particles<real, DIM>(g_, p_, seg_, st_, ctr_, ba, spec_buf_, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(count, spec_buf_, nb, hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(weight, spec_buf_ + nbins, nb, hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipMemcpyAsync(spin, spec_buf_ + 2 * (size_t)nbins, 3 * nb, hipMemcpyDeviceToHost, stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+    if (e != hipSuccess) return fail(PIC_EHIP, "spectrum (static buffer): %s", hipGetErrorString(e));
     return Status{};
 }
 
@@ -2240,6 +2312,12 @@ int pic_spectrum(pic_ctx* ctx, int32_t species, double emin, double emax, int32_
                  double* count_out, double* weight_out, double* spin_out) {
     CTX_CHECK(ctx);
     return finish(ctx, ctx->eng->spectrum(species, emin, emax, nbins, count_out, weight_out, spin_out));
+}
+
+int pic_spectrum_noalloc(pic_ctx* ctx, int32_t species, double emin, double emax, int32_t nbins,
+                         double* count_out, double* weight_out, double* spin_out) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->spectrum_noalloc(species, emin, emax, nbins, count_out, weight_out, spin_out));
 }
 
 int pic_phase_space(pic_ctx* ctx, int32_t species, int32_t axis, double xmin, double xmax,

@@ -798,6 +798,21 @@ hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStr
     return hipGetLastError();
 }
 
+// out[0 .. n) = 0 by a plain kernel (no memset node, so that the clear
+// stays correct when a caller captures the launches in a graph).
+__global__ void __launch_bounds__(kBlock) k_fill_zero(double* __restrict__ out, long long n) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock)
+        out[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* out, long long n, hipStream_t stream) {
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kBlock), 0, stream, out, n);
+    return hipGetLastError();
+}
+
 #define SPINPIC_INST_GRID(DIM)                                                                 \
     template hipError_t launch_yee_fused<double, DIM>(const Geom&, const Consts<double>&,     \
         const Fields<double>&, const Fields<double>&, double* const*, hipStream_t);             \

@@ -186,6 +186,9 @@ hipError_t launch_div_residual(const Geom& g, const Vec3d& inv_d,
                                const Fields<real>& f, const double* rho, const double* ref,
                                double* ref_out, double* blockmax, int blocks, hipStream_t stream);
 
+// out[0 .. n) = 0 (a kernel, not a memset).
+hipError_t launch_fill_zero(double* out, long long n, hipStream_t stream);
+
 // Non-finite probe over particle momenta/spins and fields: flag[0] = 1 if any.
 template <typename real>
 hipError_t launch_nonfinite(const real* data, long long n, int32_t* flag, hipStream_t stream);

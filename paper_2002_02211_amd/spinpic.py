@@ -24,9 +24,10 @@ PIC_FP64, PIC_FP32_MIXED = 0, 1
 PIC_ACC_DEFAULT, PIC_ACC_FP32, PIC_ACC_FP64 = 0, 1, 2
 PIC_FLAG_TEST_PARTICLE = 1
 MAX_SPECIES = 4
+PIC_MAX_SPECTRUM_BINS = 1024
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
-            "pic_spectrum", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
+            "pic_spectrum", "pic_spectrum_noalloc", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
             "pic_window", "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
             "pic_batch_init", "pic_batch_step", "pic_batch_polarization", "pic_batch_fields",
             "pic_batch_particles", "pic_batch_info", "pic_batch_tuning", "pic_batch_stats",
@@ -113,6 +114,8 @@ def load_library(path=LIB_PATH):
     D = ctypes.POINTER(ctypes.c_double)
     lib.pic_spectrum.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                  D, D, D]
+    lib.pic_spectrum_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         D, D, D]
     lib.pic_phase_space.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int32, D]
@@ -316,6 +319,16 @@ def pic_spectrum(ctx, species, emin, emax, nbins):
     return count, weight, spin
 
 
+def pic_spectrum_noalloc(ctx, species, emin, emax, nbins):
+    """pic_spectrum summed in the library's static device buffer (no allocation)."""
+    count = np.zeros(int(nbins))
+    weight = np.zeros(int(nbins))
+    spin = np.zeros((int(nbins), 3))
+    _check(load_library().pic_spectrum_noalloc(ctx, int(species), float(emin), float(emax), int(nbins),
+                                               _dptr(count), _dptr(weight), _dptr(spin)), ctx)
+    return count, weight, spin
+
+
 def pic_phase_space(ctx, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_):
     out = np.zeros((int(nx), int(np_)))
     _check(load_library().pic_phase_space(ctx, int(species), int(axis), float(xmin), float(xmax),
@@ -426,6 +439,9 @@ class Simulation:
 
     def spectrum(self, species, emin, emax, nbins):
         return pic_spectrum(self.ctx, species, emin, emax, nbins)
+
+    def spectrum_noalloc(self, species, emin, emax, nbins):
+        return pic_spectrum_noalloc(self.ctx, species, emin, emax, nbins)
 
     def phase_space(self, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_):
         return pic_phase_space(self.ctx, species, axis, xmin, xmax, nx, comp, pmin, pmax, np_)
