@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
                     [--precision fp32|fp64] [--no-cpu-baseline] [--no-fp64-compare]
+                    [--no-full-run] [--no-c3] [--no-c1]
     python bench.py --traffic-from FETCH.csv WRITE.csv [--workload c2] [--precision fp32]
 
 A step is one full pass of the hot path over every particle: gather, Boris
@@ -9,11 +10,18 @@ push, Thomas-BMT spin rotation, move and Esirkepov deposit (one fused kernel
 per tile), the rebinning of tile leavers, and the Yee field update.  Inputs
 are the seeded synthetic plasma of the workload (default c2: 2D3V,
 4096x1024 cells, electrons and protons at 8 per cell each, 67,108,864
-particles), resident in HBM before timing starts.  Prints one JSON line.
+particles), resident in HBM before timing starts.  Prints one JSON line;
+`value` is the throughput over the K timed steps that follow W warm-up
+steps.
 
-With FP32 particles the same workload is then run again with the FP64 path
-for the same number of steps, and its throughput and the largest difference
-of the polarization vector between the two runs are reported beside.
+The run then goes on to the workload's full length (c2: 1000 steps), with a
+read-back of every 64th particle at step 100 and the steps after it timed as
+a whole.  With FP32 particles the same schedule is run again on the FP64
+path, and the line reports the FP32-against-FP64 polarization difference at
+the end of the run and per-particle error quantiles at step 100.  The
+default c2 run adds the same for c3 (3D, 500 steps) and the absolute
+throughput of c1.  Before the GPU is touched, the CPU oracle is timed on one
+thread and on every core (up to 16 processes).
 
 ``--traffic-from`` turns two rocprofv3 counter runs of this script (one with
 ``--pmc FETCH_SIZE``, one with ``--pmc WRITE_SIZE``, each with
@@ -64,14 +72,20 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def algorithmic_bytes(ndim, precision, npart, ncells):
+def algorithmic_bytes(ndim, precision, npart, ncells, grid_bytes=None):
     """HBM bytes one push+deposit launch must move: every particle's cell,
     offsets, momentum and spin read and written, its weight read; E and B read
-    and J written once per cell (the grid is FP64 in both precisions)."""
+    and J written once per cell.  By default the grid values are counted in
+    the push precision (4 B in FP32, 8 B in FP64): 76 B per particle and 36 B
+    per cell in 2D FP32 (78.25 B per c2 push), 84 B and 36 B in 3D FP32 (93 B
+    per c3 push), 144 B and 72 B in 2D FP64.  grid_bytes = 8 counts the FP64
+    grid this library keeps in both precisions (80.5 B per c2 push, 102 B per
+    c3 push)."""
     r = 8 if precision == "fp64" else 4
+    gr = r if grid_bytes is None else grid_bytes
     read = 4 + ndim * r + 3 * r + 3 * r + r
     write = 4 + ndim * r + 3 * r + 3 * r
-    grid = 6 * 8 + 3 * 8
+    grid = 6 * gr + 3 * gr
     return (read + write) * npart + grid * ncells, read + write, grid
 
 
@@ -183,27 +197,115 @@ def cpu_model():
 
 
 def cpu_baseline(spec, state, sample_per_species):
-    """The FP64 NumPy oracle, single-threaded, pushing a bounded sample of the
+    """The FP64 NumPy oracle on one thread, pushing a bounded sample of the
     same workload's particles through gather+push+spin+deposit once."""
-    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ.setdefault(var, "1")
-    import numpy as np
+    from threadpoolctl import threadpool_limits
     import oracle
     sub = {"particles": [p[:sample_per_species] for p in state["particles"]],
            "fields": state["fields"]}
-    sim = oracle.Sim(spec, sub)
-    n = sum(p.shape[0] for p in sub["particles"])
-    t0 = time.perf_counter()
-    for k in range(len(spec["species"])):
-        m = sim.xi[k].shape[0]
-        for lo in range(0, m, sim.CHUNK):
-            sim.push_species(k, lo, min(m, lo + sim.CHUNK))
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        sim = oracle.Sim(spec, sub)
+        n = sum(p.shape[0] for p in sub["particles"])
+        t0 = time.perf_counter()
+        for k in range(len(spec["species"])):
+            m = sim.xi[k].shape[0]
+            for lo in range(0, m, sim.CHUNK):
+                sim.push_species(k, lo, min(m, lo + sim.CHUNK))
+        dt = time.perf_counter() - t0
     del sim
     return {"value": n / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
             "sample": "%d particles (%d per species, first rows of the same seeded %s state), "
                       "one gather+push+spin+deposit pass, FP64 NumPy, one thread of %s, %.1f s"
                       % (n, sample_per_species, spec["name"], cpu_model(), dt)}
+
+
+def cpu_workers():
+    """Processes for the all-cores oracle baseline: the CPUs this process may
+    run on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+_SHARED = {}   # what forked oracle workers read: the workload and its state
+
+
+def _oracle_worker(w, ranges, barrier, queue, shm_name, ncells):
+    """One process of the all-cores baseline: its particle ranges pushed by
+    the oracle on one thread, its current written into its slot of the
+    shared array."""
+    from multiprocessing import shared_memory
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle
+    spec, state = _SHARED["spec"], _SHARED["state"]
+    sub = {"particles": [p[lo:hi] for p, (lo, hi) in zip(state["particles"], ranges)],
+           "fields": state["fields"]}
+    with threadpool_limits(limits=1):
+        sim = oracle.Sim(spec, sub)
+        barrier.wait()
+        t0 = time.time()
+        for k in range(len(spec["species"])):
+            m = sim.xi[k].shape[0]
+            for lo in range(0, m, sim.CHUNK):
+                sim.push_species(k, lo, min(m, lo + sim.CHUNK))
+        shm = shared_memory.SharedMemory(name=shm_name)
+        J = np.ndarray((3, ncells), dtype=np.float64, buffer=shm.buf, offset=w * 3 * ncells * 8)
+        J[...] = sim.J.reshape(3, ncells)
+        del J
+        shm.close()
+        t1 = time.time()
+    queue.put((w, t0, t1, sum(x.shape[0] for x in sim.xi)))
+
+
+def cpu_baseline_all_cores(spec, state):
+    """The FP64 NumPy oracle on every core: the whole workload's particles,
+    each species cut into P contiguous ranges, pushed by P forked processes
+    (one thread each) through gather+push+spin+deposit once; the P current
+    arrays are then summed.  Timed from the common start to the summed J.
+    Must run before this process touches the GPU (the workers are forks)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    import numpy as np
+    P = cpu_workers()
+    ncells = int(np.prod(state["fields"].shape[1:]))
+    _SHARED["spec"], _SHARED["state"] = spec, state
+    ctx = mp.get_context("fork")
+    barrier = ctx.Barrier(P + 1)
+    queue = ctx.Queue()
+    shm = shared_memory.SharedMemory(create=True, size=P * 3 * ncells * 8)
+    procs = []
+    try:
+        for w in range(P):
+            ranges = []
+            for p in state["particles"]:
+                m = p.shape[0]
+                ranges.append((m * w // P, m * (w + 1) // P))
+            pr = ctx.Process(target=_oracle_worker, args=(w, ranges, barrier, queue, shm.name, ncells))
+            pr.start()
+            procs.append(pr)
+        barrier.wait()
+        res = [queue.get(timeout=600) for _ in range(P)]
+        for pr in procs:
+            pr.join()
+        t_sum0 = time.time()
+        Jall = np.ndarray((P, 3, ncells), dtype=np.float64, buffer=shm.buf)
+        J = Jall.sum(axis=0)
+        t_sum = time.time() - t_sum0
+        del Jall
+    finally:
+        shm.close()
+        shm.unlink()
+        _SHARED.clear()
+    n = sum(r[3] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res) + t_sum
+    return {"value": n / wall, "unit": "pushes/s", "cores": P, "kind": "oracle",
+            "sample": "all %d particles of the seeded %s state, each species cut into %d contiguous ranges, "
+                      "%d processes of one thread each on %s, one gather+push+spin+deposit pass, then the %d "
+                      "current arrays summed; %.1f s wall (J sum %.2f s, |J|max %.3e)"
+                      % (n, spec["name"], P, P, cpu_model(), P, wall, t_sum, float(np.abs(J).max()))}
 
 
 def time_diagnostics(sim, spec, npart, precision, reps=5):
@@ -466,42 +568,138 @@ def window_kw(spec, shift_cells):
                 ramp_len=pl["ramp_len"] if pl["profile"] == "ramp" else 0.0, s0=pl["s0"])
 
 
-def run_gpu(S, spec, state, precision, acc, warmup, steps, tile=None, window=False, slack=0.0):
-    """Initialize, warm up, time `steps` steps; returns (sim, cfg, elapsed s, timers)."""
+def thermal_floor(spec, k):
+    """Momentum floor for relative errors: the species' thermal spread."""
+    T = spec.get("plasma", {}).get("T_keV", 1.0)
+    return math.sqrt(T / (spec["species"][k]["mu"] * 510.99895))
+
+
+def particle_errors(got, want, spec, k):
+    """Per-particle differences of two read-backs of the same particles (rows
+    id, x y z, u, s, w, same ids): position in cells (periodic), momentum
+    relative to max(|u|, u_thermal), spin absolute; the largest of the three."""
+    import numpy as np
+    if got.shape != want.shape or not np.array_equal(got[:, 0], want[:, 0]):
+        raise SystemExit("bench: the two runs' particle samples do not hold the same ids")
+    pos = np.zeros(got.shape[0])
+    for a in range(spec["ndim"]):
+        L = spec["n"][a] * spec["d"][a]
+        dx = np.abs(got[:, 1 + a] - want[:, 1 + a])
+        pos = np.maximum(pos, np.minimum(dx, L - dx) / spec["d"][a])
+    umag = np.max(np.abs(want[:, 4:7]), axis=1)
+    mom = np.max(np.abs(got[:, 4:7] - want[:, 4:7]), axis=1) / np.maximum(umag, thermal_floor(spec, k))
+    spin = np.max(np.abs(got[:, 7:10] - want[:, 7:10]), axis=1)
+    return np.maximum(np.maximum(pos, mom), spin)
+
+
+def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, window=False, slack=0.0,
+                 full_steps=None, sample_step=100, sample_stride=64, on_open=None):
+    """One run of a workload.  Init; `warmup` steps; `steps` timed steps
+    (events around the push kernel only: events between every kernel would
+    lengthen the step); BREAKDOWN_STEPS steps with events around every kernel
+    (the other kernels' times).  With full_steps: on to step sample_step,
+    where every sample_stride-th particle (by id) of each species is read
+    back, then on to step full_steps, timed as a whole with the push events
+    on (overflow pushes, insertions and repacks of the later, laser-driven
+    plasma included), and the polarization of the last step.  on_open(sim),
+    if given, runs last; its result is kept as "extra".  The context is freed
+    before returning."""
+    import numpy as np
     import torch
+    out = {"precision": precision}
     cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile, slack=slack)
     t0 = time.time()
     sim = S.Simulation(cfg, state["particles"], state["fields"])
     if window:
         sim.window(**window_kw(spec, sim.stats()["tile"][0]))
     torch.cuda.synchronize()
-    print("[bench] %s init (sort + upload) %.1f s" % (precision, time.time() - t0),
+    print("[bench] %s %s init (sort + upload) %.1f s" % (spec["name"], precision, time.time() - t0),
           file=sys.stderr, flush=True)
     sim.step(warmup)
     torch.cuda.synchronize()
-    print("[bench] %s warmup done" % precision, file=sys.stderr, flush=True)
-    # events around the push kernel only in the timed region (events between
-    # every kernel would lengthen the step); the other kernels' times come
-    # from BREAKDOWN_STEPS further steps
     sim.timing(True, push_only=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    out["elapsed"] = time.perf_counter() - t0
     timers = sim.timing_read()
     sim.timing(True)
     sim.step(BREAKDOWN_STEPS)
     rest = sim.timing_read()
     sim.timing(False)
-    timers = {k: (timers[k] if k == "push_deposit" else rest[k]) for k in timers}
-    return sim, cfg, elapsed, timers
+    out["timers"] = {k: (timers[k] if k == "push_deposit" else rest[k]) for k in timers}
+    if timers["push_deposit"][1] != steps:
+        raise SystemExit("bench: %d push launches timed for %d steps" % (timers["push_deposit"][1], steps))
+    done = warmup + steps + BREAKDOWN_STEPS
+    out["stats_timed"] = sim.stats()
+    out["P_timed"], _ = sim.polarization()
+    if full_steps:
+        if done < sample_step:
+            sim.step(sample_step - done)
+            done = sample_step
+        out["sample_step"] = done
+        out["sample"] = [sim.particles(k)[::sample_stride].copy() for k in range(len(spec["species"]))]
+        print("[bench] %s %s: sample of every %dth particle read at step %d"
+              % (spec["name"], precision, sample_stride, done), file=sys.stderr, flush=True)
+        left = full_steps - done
+        sim.timing(True, push_only=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(left)
+        torch.cuda.synchronize()
+        out["rest_elapsed"] = time.perf_counter() - t0
+        out["rest_steps"] = left
+        late = sim.timing_read()
+        sim.timing(False)
+        out["rest_push"] = late["push_deposit"]
+        if late["push_deposit"][1] != left:
+            raise SystemExit("bench: %d push launches in the last %d steps" % (late["push_deposit"][1], left))
+        done = full_steps
+        print("[bench] %s %s: %d further steps in %.2f s" % (spec["name"], precision, left, out["rest_elapsed"]),
+              file=sys.stderr, flush=True)
+    st = sim.stats()
+    if st["steps"] != done:
+        raise SystemExit("bench: the context counted %d steps, the schedule %d" % (st["steps"], done))
+    out["stats"] = st
+    out["steps_done"] = done
+    out["P"], out["N"] = sim.polarization()
+    out["ctx"] = sim.ctx.value or 0
+    if on_open is not None:
+        out["extra"] = on_open(sim)
+    sim.close()
+    del sim
+    torch.cuda.synchronize()
+    return out
+
+
+def compare_runs(spec, r32, r64):
+    """FP32-mixed against FP64 on the same workload and step schedule."""
+    import numpy as np
+    P32, P64 = np.asarray(r32["P"]), np.asarray(r64["P"])
+    res = {"after_steps": r32["steps_done"],
+           "dP_max_fp32_vs_fp64": float(np.max(np.abs(P32 - P64))),
+           "P_fp32": [float(v) for v in P32], "P_fp64": [float(v) for v in P64],
+           # the two runs are separate contexts whose step counters both read the full run
+           "self_check": {"steps_fp32": int(r32["stats"]["steps"]), "steps_fp64": int(r64["stats"]["steps"]),
+                          "distinct_contexts": r32["ctx"] != r64["ctx"] or r32["ctx"] == 0,
+                          "P_bitwise_identical": bool(np.array_equal(P32, P64))}}
+    if "sample" in r32:
+        per = {}
+        for k, sp in enumerate(spec["species"]):
+            e = particle_errors(r32["sample"][k], r64["sample"][k], spec, k)
+            per[sp.get("name", str(k))] = {
+                "particles": int(e.size), "median": float(np.median(e)),
+                "q99": float(np.percentile(e, 99)), "max": float(e.max())}
+        res["per_particle_fp32_vs_fp64"] = dict(per, after_steps=r32["sample_step"],
+                                                sampled="every 64th particle by id")
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOAD_TEXT),
                     help="c1-c3: PIC steps; c4: differentiable tracking (forward + adjoint per step); "
@@ -527,6 +725,11 @@ def main():
                          "workload's plasma, shift by one tile column)")
     ap.add_argument("--batch-only", action="store_true",
                     help="c5: time the autotuned batch only (no default-tile batch, no sequential runs)")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="stop after the timed steps (no run to the workload's full length, no per-particle sample)")
+    ap.add_argument("--no-c3", action="store_true", help="c2: skip the c3 sub-object")
+    ap.add_argument("--no-c1", action="store_true", help="c2: skip the c1 sub-object")
+    ap.add_argument("--no-all-cores", action="store_true", help="skip the all-cores oracle baseline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -546,8 +749,29 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import synth
+
+    spec = state = None
+    cpu = {}
+    if args.workload in ("c1", "c2", "c3"):
+        spec = synth.preset(args.workload)
+        t0 = time.time()
+        state = synth.make_state(spec)
+        print("[bench] %s: %d particles generated in %.1f s"
+              % (args.workload, sum(p.shape[0] for p in state["particles"]), time.time() - t0),
+              file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            # on the host cores, before this process touches the GPU: the
+            # all-cores leg forks its workers
+            sample = min(args.cpu_sample, min(p.shape[0] for p in state["particles"]))
+            cpu["one"] = cpu_baseline(spec, state, sample)
+            print("[bench] cpu baseline, one thread: %.3g pushes/s" % cpu["one"]["value"], file=sys.stderr, flush=True)
+            if not args.no_all_cores:
+                cpu["all"] = cpu_baseline_all_cores(spec, state)
+                print("[bench] cpu baseline, %d processes: %.3g pushes/s" % (cpu["all"]["cores"], cpu["all"]["value"]),
+                      file=sys.stderr, flush=True)
+
+    import torch
     from paper_2002_02211_amd import spinpic as S
 
     if not torch.cuda.is_available():
@@ -564,50 +788,40 @@ def main():
         del a, b
 
     if args.workload == "c4":
-        if args.steps == 100 and args.warmup == 10:
+        if args.steps == 50 and args.warmup == 10:
             args.steps, args.warmup = 5, 1
         bench_tracking(args)
         return
     if args.workload == "c5":
-        if args.steps == 100 and args.warmup == 10:
+        if args.steps == 50 and args.warmup == 10:
             args.steps = 300
         bench_batch(args)
         return
 
-    spec = synth.preset(args.workload)
     precision = args.precision or spec["precision"]
-    t0 = time.time()
-    state = synth.make_state(spec)
     npart = sum(p.shape[0] for p in state["particles"])
-    print("[bench] %s: %d particles generated in %.1f s" % (args.workload, npart, time.time() - t0),
-          file=sys.stderr, flush=True)
-
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    sim, cfg, elapsed, timers = run_gpu(S, spec, state, precision, acc, args.warmup, args.steps, tile,
-                                        window=args.window, slack=args.slack)
-    stats = sim.stats()
+    full = None if (args.window or args.no_full_run) else spec["steps"]
+    diag = (lambda sim: time_diagnostics(sim, spec, npart, precision)) if args.diagnostics else None
+    r = run_schedule(S, spec, state, precision, acc, args.warmup, args.steps, tile, window=args.window,
+                     slack=args.slack, full_steps=full, on_open=diag)
+    stats = r["stats_timed"]
     if args.window:
         npart = stats["particles"]   # injected minus removed since the start
-    P, N = sim.polarization()
-    print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s N=%d"
-          % (args.steps, elapsed, json.dumps(timers), stats, P, N), file=sys.stderr, flush=True)
+    timers = r["timers"]
+    print("[bench] timed %d steps in %.3f s; kernels %s; stats %s; P=%s"
+          % (args.steps, r["elapsed"], json.dumps(timers), stats, r["P_timed"]), file=sys.stderr, flush=True)
 
-    ncells = int(spec["n"][0]) * int(spec["n"][1]) * (int(spec["n"][2]) if spec["ndim"] == 3 else 1)
-    launch_bytes, per_particle, per_cell = algorithmic_bytes(spec["ndim"], precision, npart, ncells)
-    push_ms, push_n = timers["push_deposit"]
-    avg_push_s = push_ms / 1e3 / max(push_n, 1)
-    achieved = launch_bytes / avg_push_s / 1e9
-    traffic = measured_traffic(args.workload, precision, launch_bytes)
-
+    ncells = int(np.prod(state["fields"].shape[1:]))
     result = {
         "metric": METRIC,
-        "value": npart * args.steps / elapsed,
+        "value": npart * args.steps / r["elapsed"],
         "unit": "pushes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": r["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -620,44 +834,116 @@ def main():
                    "tile": list(stats["tile"])[: spec["ndim"]],
                    **({"moving_window": dict(window_kw(spec, stats["tile"][0]), shifts=stats["shifts"])}
                       if args.window else {})},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_push_tiles (gather+Boris+T-BMT+move+Esirkepov deposit)",
-                     "bytes_per_launch": launch_bytes,
-                     "bytes_per_particle": per_particle, "bytes_per_cell": per_cell,
-                     "avg_launch_ms": avg_push_s * 1e3,
-                     "push_pushes_per_s": npart / avg_push_s},
+        "roofline": push_roofline(args.workload, spec, precision, npart, ncells, timers["push_deposit"]),
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
         "store": {"overflow_particles": stats["overflow"], "repacks": stats["repacks"],
                   "after_steps": args.warmup + args.steps + BREAKDOWN_STEPS},
     }
-    if args.diagnostics:
-        result["diagnostics"] = time_diagnostics(sim, spec, npart, precision)
-    sim.close()
-    del sim
-    torch.cuda.synchronize()
+    if full:
+        result["full_run"] = full_run_summary(r, npart)
+    if "extra" in r:
+        result["diagnostics"] = r["extra"]
 
     if precision == "fp32" and not args.no_fp64_compare:
-        sim64, _, el64, tm64 = run_gpu(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile,
-                                       window=args.window, slack=args.slack)
-        P64, _ = sim64.polarization()
-        sim64.close()
-        del sim64
-        torch.cuda.synchronize()
+        r64 = run_schedule(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile,
+                           window=args.window, slack=args.slack, full_steps=full)
+        t64 = r64["timers"]["push_deposit"][0] / 1e3 / max(r64["timers"]["push_deposit"][1], 1)
         lb64, _, _ = algorithmic_bytes(spec["ndim"], "fp64", npart, ncells)
-        t64 = tm64["push_deposit"][0] / 1e3 / max(tm64["push_deposit"][1], 1)
-        result["fp64_compare"] = {
-            "value": npart * args.steps / el64, "unit": "pushes/s",
-            "ms_per_step": el64 / args.steps * 1e3,
-            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
-            "dP_max_fp32_vs_fp64": float(np.max(np.abs(np.asarray(P) - np.asarray(P64)))),
-            "P_fp32": [float(v) for v in P], "P_fp64": [float(v) for v in P64],
-            "after_steps": args.warmup + args.steps + BREAKDOWN_STEPS}
+        result["fp64_compare"] = dict({
+            "value": npart * args.steps / r64["elapsed"], "unit": "pushes/s",
+            "ms_per_step": r64["elapsed"] / args.steps * 1e3,
+            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS},
+            **compare_runs(spec, r, r64))
+        if full:
+            result["fp64_compare"]["full_run"] = full_run_summary(r64, npart)
+        del r64
+    del r
+    state = None
 
-    if not args.no_cpu_baseline:
-        sample = min(args.cpu_sample, min(p.shape[0] for p in state["particles"]))
-        result["cpu_baseline"] = cpu_baseline(spec, state, sample)
+    if args.workload == "c2" and not args.no_c3:
+        result["c3"] = bench_other(S, "c3", args, compare=not args.no_fp64_compare)
+    if args.workload == "c2" and not args.no_c1:
+        result["c1"] = bench_other(S, "c1", args, compare=False)
+
+    if cpu:
+        result["cpu_baseline"] = cpu.get("all", cpu["one"])
+        if "all" in cpu:
+            result["cpu_baseline_one_thread"] = cpu["one"]
     print(json.dumps(result), flush=True)
+
+
+def push_roofline(workload, spec, precision, npart, ncells, push_timer):
+    """The push kernel against HBM: algorithmic bytes per launch (grid values
+    in the push precision, as the byte model counts them; the figure with the
+    FP64 grid this library keeps beside it) over the mean launch time from
+    the HIP events."""
+    push_ms, push_n = push_timer
+    avg = push_ms / 1e3 / max(push_n, 1)
+    lb, per_particle, per_cell = algorithmic_bytes(spec["ndim"], precision, npart, ncells)
+    lb8, pp8, pc8 = algorithmic_bytes(spec["ndim"], precision, npart, ncells, grid_bytes=8)
+    achieved = lb / avg / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, precision, lb),
+            "kernel": "k_push_tiles (gather+Boris+T-BMT+move+Esirkepov deposit)",
+            "bytes_per_launch": lb, "bytes_per_particle": per_particle, "bytes_per_cell": per_cell,
+            "bytes_per_push": lb / npart,
+            "fp64_grid": {"bytes_per_launch": lb8, "bytes_per_push": lb8 / npart,
+                          "frac": lb8 / avg / 1e9 / HBM_PEAK_GBS},
+            "avg_launch_ms": avg * 1e3, "push_pushes_per_s": npart / avg}
+
+
+def full_run_summary(r, npart):
+    """The steps after the sample to the end of the run, timed as a whole."""
+    push_ms, push_n = r["rest_push"]
+    st = r["stats"]
+    return {"steps": r["steps_done"], "timed_steps": r["rest_steps"],
+            "from_step": r["steps_done"] - r["rest_steps"],
+            "ms_per_step": r["rest_elapsed"] / r["rest_steps"] * 1e3,
+            "pushes_per_s": npart * r["rest_steps"] / r["rest_elapsed"],
+            "push_avg_launch_ms": push_ms / max(push_n, 1),
+            "overflow_particles_at_end": st["overflow"], "repacks": st["repacks"],
+            "particles_moved_tile": st["moved"], "P_end": [float(v) for v in r["P"]]}
+
+
+def bench_other(S, workload, args, compare):
+    """Another PIC workload in the same run: throughput over the timed steps,
+    the push roofline, the whole run to its full length and, with compare, the
+    FP64 run of the same schedule against it."""
+    import numpy as np
+    import synth
+    spec = synth.preset(workload)
+    t0 = time.time()
+    state = synth.make_state(spec)
+    npart = sum(p.shape[0] for p in state["particles"])
+    ncells = int(np.prod(state["fields"].shape[1:]))
+    print("[bench] %s: %d particles generated in %.1f s" % (workload, npart, time.time() - t0),
+          file=sys.stderr, flush=True)
+    precision = spec["precision"]
+    r = run_schedule(S, spec, state, precision, S.PIC_ACC_DEFAULT, args.warmup, args.steps,
+                     full_steps=spec["steps"])
+    timers = r["timers"]
+    out = {"workload": "%s: %s" % (workload, WORKLOAD_TEXT[workload]), "particles": npart, "cells": ncells,
+           "precision": precision, "tile": list(r["stats_timed"]["tile"])[: spec["ndim"]],
+           "value": npart * args.steps / r["elapsed"], "unit": "pushes/s", "steps": args.steps,
+           "ms_per_step": r["elapsed"] / args.steps * 1e3,
+           "roofline": push_roofline(workload, spec, precision, npart, ncells, timers["push_deposit"]),
+           "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in timers.items()},
+           "full_run": full_run_summary(r, npart)}
+    if workload == "c1":
+        out["note"] = "c1's 20 MB of state stays in the 256 MB last-level cache: absolute pushes/s only"
+        out["roofline"]["frac"] = None
+        out["roofline"]["fp64_grid"]["frac"] = None
+    if compare and precision == "fp32":
+        r64 = run_schedule(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps,
+                           full_steps=spec["steps"])
+        t64 = r64["timers"]["push_deposit"][0] / 1e3 / max(r64["timers"]["push_deposit"][1], 1)
+        lb64, _, _ = algorithmic_bytes(spec["ndim"], "fp64", npart, ncells)
+        out["fp64_compare"] = dict({
+            "value": npart * args.steps / r64["elapsed"], "unit": "pushes/s",
+            "ms_per_step": r64["elapsed"] / args.steps * 1e3,
+            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "full_run": full_run_summary(r64, npart)}, **compare_runs(spec, r, r64))
+    return out
 
 
 if __name__ == "__main__":

@@ -520,6 +520,7 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     kf_.dt = dt;
     for (int a = 0; a < 3; ++a) {
         k_.dt_d[a] = (real)(dt / d_[a]);
+        k_.dt_d_lo[a] = (real)(dt / d_[a] - (double)k_.dt_d[a]);
         k_.d_dt[a] = (real)(d_[a] / dt);
         kf_.cb[a] = 0.5 * dt / d_[a];
         kf_.ce[a] = dt / d_[a];
@@ -1634,6 +1635,7 @@ Status BatchEngine<real>::upload_descs() {
         D.kf.dt = c.dt;
         for (int a = 0; a < 3; ++a) {
             D.k.dt_d[a] = (real)(c.dt / R.d[a]);
+            D.k.dt_d_lo[a] = (real)(c.dt / R.d[a] - (double)D.k.dt_d[a]);
             D.k.d_dt[a] = (real)(R.d[a] / c.dt);
             D.kf.cb[a] = 0.5 * c.dt / R.d[a];
             D.kf.ce[a] = c.dt / R.d[a];

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace spinpic {
 
 constexpr int kMaxSpecies = 4;
@@ -63,6 +65,8 @@ template <typename real>
 struct Consts {
     real dt;
     real dt_d[3];     // dt / d_a: displacement in cells per unit velocity
+    real dt_d_lo[3];  // dt / d_a - dt_d[a] (0 in FP64): the rounding of dt_d, so that
+                      // FP32 moves carry no systematic drift of one rounding per step
     real d_dt[3];     // d_a / dt: Esirkepov current scale
     real eps[kMaxSpecies];   // r dt / 2 with r = Z / mu
     real r[kMaxSpecies];
@@ -71,6 +75,7 @@ struct Consts {
     real cb[3];       // (dt / 2) / d_a  (B half step)
     real ce[3];       // dt / d_a        (E step)
     real mur_k;       // (c dt - dx) / (c dt + dx), Mur's coefficient at open x faces
+    double fx_scale;  // deterministic mode: units per 1 of the fixed-point current (0: off)
 };
 
 struct Segs {
@@ -87,10 +92,25 @@ enum {
     CTR_LEAVE0 = 0,   // leavers of even steps
     CTR_LEAVE1 = 1,   // leavers of odd steps
     CTR_STASH = 2,    // particles in the overflow store
+    CTR_NONFINITE = 3,  // set to 1 by a push that produced a non-finite momentum or spin
     CTR_QUEUE = 8,    // next work item of the batched push: 8 per XCD queue,
                       // even steps at CTR_QUEUE, odd steps at CTR_QUEUE + 8
     CTR_NCTR = 24
 };
+
+// ---------------------------------------------------------------- fixed point
+//
+// The deterministic mode sums currents as 64-bit integers: a contribution v
+// becomes rint(v * scale) (two's complement in an unsigned word, so that
+// the hardware's unsigned atomic add does signed sums).  Integer sums do not
+// depend on the order of the additions, so the result is the same on every
+// run; scale is a power of two chosen so that no node's sum can pass 2^62.
+template <typename acc_t>
+inline constexpr bool kFixedAcc = std::is_same<acc_t, unsigned long long>::value;
+
+__device__ inline unsigned long long to_fixed(double v, double scale) {
+    return (unsigned long long)__double2ll_rn(v * scale);
+}
 
 // ---------------------------------------------------------------- cells
 
@@ -141,12 +161,22 @@ __device__ inline float fsqrt(float x) { return sqrtf(x); }
 __device__ inline double fsqrt(double x) { return sqrt(x); }
 
 // Reciprocal and reciprocal square root of arguments >= 1.  FP64 keeps the
-// correctly rounded division and square root; FP32 uses the hardware
-// approximations v_rcp_f32 and v_rsq_f32 (about 1 ulp), well inside the
-// FP32 error budget and a fraction of the cost of IEEE division.
-__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+// correctly rounded division and square root.  FP32 takes the hardware
+// approximations v_rcp_f32 and v_rsq_f32 (about 1 ulp) and refines each by
+// one Newton step (two fused multiply-adds), a fraction of the cost of IEEE
+// division.  Unrefined, their error is biased: a particle that keeps about
+// the same gamma gets the same error in 1/gamma every step, and over 100
+// steps its position drifted by twice what float32 storage costs.
+__device__ inline float recip(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, y, 1.0f), y, y);          // y (2 - x y)
+}
 __device__ inline double recip(double x) { return 1.0 / x; }
-__device__ inline float rsqrt1(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float rsqrt1(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float h = 0.5f * x * y;
+    return fmaf(fmaf(-h, y, 0.5f), y, y);          // y (3/2 - x y^2 / 2)
+}
 __device__ inline double rsqrt1(double x) { return 1.0 / sqrt(x); }
 
 template <typename real>
@@ -292,10 +322,12 @@ __device__ inline void gather_all(const Src& F, const Stencil1<real> st[3], real
 template <typename real>
 __device__ inline void boris_tbmt(real u[3], real s[3], const real E[3], const real B[3],
                                   real eps, real r, real a, real half_dt) {
-    real um[3], t[3], up[3], tmp[3], uprime[3];
-    um[0] = u[0] + eps * E[0];
-    um[1] = u[1] + eps * E[1];
-    um[2] = u[2] + eps * E[2];
+    real kick[3], um[3], t[3], rot[3], tmp[3], uprime[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        kick[q] = eps * E[q];
+        um[q] = u[q] + kick[q];
+    }
     const real g2 = real(1) + dot3(um, um);
     const real igm = rsqrt1(g2);
     const real gm = g2 * igm;
@@ -309,16 +341,16 @@ __device__ inline void boris_tbmt(real u[3], real s[3], const real E[3], const r
     uprime[2] = um[2] + tmp[2];
     const real sfac = real(2) * recip(real(1) + dot3(t, t));
     cross(uprime, t, tmp);
-    up[0] = um[0] + sfac * tmp[0];
-    up[1] = um[1] + sfac * tmp[1];
-    up[2] = um[2] + sfac * tmp[2];
+    // rot = u+ - u-, the magnetic rotation's change of u
+    rot[0] = sfac * tmp[0];
+    rot[1] = sfac * tmp[1];
+    rot[2] = sfac * tmp[2];
 
     // Thomas-BMT precession vector at gamma-, beta = (u- + u+)/(2 gamma-)
+    // = (u- + rot/2)/gamma-
     real beta[3], bxe[3], Om[3], tau[3], sprime[3];
-    const real hb = real(0.5) * igm;
-    beta[0] = (um[0] + up[0]) * hb;
-    beta[1] = (um[1] + up[1]) * hb;
-    beta[2] = (um[2] + up[2]) * hb;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) beta[q] = (um[q] + real(0.5) * rot[q]) * igm;
     const real igp1 = recip(gm + real(1));
     const real Omega_B = a + igm;
     const real Omega_v = a * gm * igp1;
@@ -342,9 +374,18 @@ __device__ inline void boris_tbmt(real u[3], real s[3], const real E[3], const r
     s[1] = s[1] + sf * tmp[1];
     s[2] = s[2] + sf * tmp[2];
 
-    u[0] = up[0] + eps * E[0];
-    u[1] = up[1] + eps * E[1];
-    u[2] = up[2] + eps * E[2];
+    // u^(n+1/2) = u+ + eps E = u + (2 eps E + rot): the step's change is
+    // summed at its own scale and added to u once, so that u (large for a
+    // relativistic particle) takes one rounding per step instead of three
+#pragma unroll
+    for (int q = 0; q < 3; ++q) u[q] = u[q] + ((kick[q] + kick[q]) + rot[q]);
+}
+
+// Displacement in cells along axis a for velocity v: v dt / d_a with the
+// step constant in two parts (exact in FP64, where the low part is 0).
+template <typename real>
+__device__ inline real displacement(real v, const Consts<real>& k, int a) {
+    return fma(v, k.dt_d[a], v * k.dt_d_lo[a]);
 }
 
 // Advance one offset by disp cells (|disp| < 1); returns the cell change

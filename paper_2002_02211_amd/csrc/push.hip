@@ -7,15 +7,20 @@
 namespace spinpic {
 
 // Current sink into the shared-memory J tile.  Node l of the tile (local
-// index, -1 .. T+1) is shared-memory coordinate l + 1.
+// index, -1 .. T+1) is shared-memory coordinate l + 1.  With acc_t a 64-bit
+// unsigned word (the deterministic mode) every contribution is added as the
+// fixed-point integer to_fixed(v, fscale).
 template <typename acc_t, int DIM>
 struct TileJ {
     acc_t* base;
     int Hx, Hxy, H;
     int o;   // offset of the stencil's base node
+    double fscale;
     template <typename real>
     __device__ inline void add(int c, int i, int j, int k, real v) const {
-        atomicAdd(base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i, (acc_t)v);
+        acc_t* q = base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i;
+        if constexpr (kFixedAcc<acc_t>) atomicAdd(q, to_fixed((double)v, fscale));
+        else atomicAdd(q, (acc_t)v);
     }
     template <typename real>
     __device__ inline void add_nz(int c, int i, int j, int k, real v) const {
@@ -24,13 +29,15 @@ struct TileJ {
 };
 
 // Current sink straight into global J with periodic wrap (current beyond
-// open x faces is dropped).
+// open x faces is dropped).  fscale != 0: the deterministic mode, J holds
+// fixed-point integers during the push (see to_fixed).
 template <typename freal, int DIM>
 struct GlobalJ {
     freal* J[3];
     int n[3];
     int b[3];  // absolute base node
     int open_x;
+    double fscale;
     template <typename real>
     __device__ inline void add_nz(int c, int i, int j, int k, real v) const {
         if (v != real(0)) add(c, i, j, k, v);
@@ -41,7 +48,9 @@ struct GlobalJ {
         const int ix = wrap_index(b[0] + i, n[0]);
         const int iy = wrap_index(b[1] + j, n[1]);
         const int iz = DIM == 3 ? wrap_index(b[2] + k, n[2]) : 0;
-        atomicAdd(J[c] + ((long long)iz * n[1] + iy) * n[0] + ix, (freal)v);
+        freal* q = J[c] + ((long long)iz * n[1] + iy) * n[0] + ix;
+        if (fscale != 0.0) atomicAdd(reinterpret_cast<unsigned long long*>(q), to_fixed((double)v, fscale));
+        else atomicAdd(q, (freal)v);
     }
 };
 
@@ -233,7 +242,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
             const real wgt = w_n;
             if (base + kBlock < n) load(start, min(i + kBlock, n - 1));
 
-            bool leave = false;
+            bool leave = false, bad = false;
             int newcell = cell0;
             if (active) {
                 int c[3];
@@ -246,6 +255,9 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
                 real E[3], B[3];
                 gather_all(TF, st, E, B);
                 boris_tbmt(u, s, E, B, eps, r, an, half_dt);
+                // non-finite probe: a NaN or infinity anywhere in u or s
+                // makes this sum non-finite
+                bad = !__builtin_isfinite(dot3(u, u) + dot3(s, s));
 
                 const real ig = rsqrt1(real(1) + dot3(u, u));
                 real o0[3];
@@ -253,7 +265,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
                     o0[a] = o[a];
-                    dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+                    dc[a] = advance_offset(o[a], displacement(u[a] * ig, k, a));
                 }
                 if (deposit) {
                     real S0[3][3], S1[3][3], q[3];
@@ -264,7 +276,8 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
                         q[a] = -Z * wgt * k.d_dt[a];
                     }
                     TileJ<acc_t, DIM> sink{Jl, Hx, Hxy, H,
-                                           (DIM == 3 ? (b[2] + 1) * Hxy : 0) + (b[1] + 1) * Hx + (b[0] + 1)};
+                                           (DIM == 3 ? (b[2] + 1) * Hxy : 0) + (b[1] + 1) * Hx + (b[0] + 1),
+                                           k.fx_scale};
                     esirkepov<real, DIM>(S0, S1, dc, q, Z * wgt * u[2] * ig, sink);
                 }
                 if (dc[0] | dc[1] | dc[2]) {
@@ -303,7 +316,11 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
                 sto(p.s[a], br, s[a]);
             }
             const unsigned long long m = __ballot(leave);
-            if (lane == 0) leavemask[(base >> 6) + wave] = m;
+            const unsigned long long nf = __ballot(bad);
+            if (lane == 0) {
+                leavemask[(base >> 6) + wave] = m;
+                if (nf) ctr[CTR_NONFINITE] = 1;
+            }
         }
         __syncthreads();
 
@@ -411,7 +428,12 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const acc_t v = Jl[c * H + li];
-                        if (v != acc_t(0)) atomicAdd(f.J[c] + gi, (freal)v);
+                        if (v != acc_t(0)) {
+                            if constexpr (kFixedAcc<acc_t>)
+                                atomicAdd(reinterpret_cast<unsigned long long*>(f.J[c] + gi), v);
+                            else
+                                atomicAdd(f.J[c] + gi, (freal)v);
+                        }
                     }
                 }
             }
@@ -471,13 +493,15 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
     real E[3], B[3];
     gather_all(GF, stc, E, B);
     boris_tbmt(u, s, E, B, k.eps[sp], k.r[sp], k.a[sp], half_dt);
-    const real ig = real(1) / fsqrt(real(1) + dot3(u, u));
+    // the same arithmetic as the tile push, so that a particle gets the same
+    // result whichever of the two pushes it
+    const real ig = rsqrt1(real(1) + dot3(u, u));
     real o0[3];
     int dc[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         o0[a] = o[a];
-        dc[a] = advance_offset(o[a], u[a] * ig * k.dt_d[a]);
+        dc[a] = advance_offset(o[a], displacement(u[a] * ig, k, a));
     }
     if (deposit) {
         real S0[3][3], S1[3][3], q[3];
@@ -489,6 +513,7 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
             sink.b[a] = 0;
         }
         sink.open_x = g.open_x;
+        sink.fscale = k.fx_scale;
         const real Z = k.Z[sp];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {

@@ -9,6 +9,6 @@ both the HIP library and the oracle receive its output as plain arrays.
 from .workloads import (  # noqa: F401
     LAMBDA, ME_C2_MEV, MP_OVER_ME, A_E, A_P,
     electron, proton, courant_dt, preset, PRESETS,
-    make_particles, make_laser_fields, make_state, grid_shape,
+    make_particles, make_laser_fields, make_state, grid_shape, make_static_fields,
     MICRON, tracking_preset, make_beam, batch_specs,
 )

@@ -232,6 +232,43 @@ def make_laser_fields(spec):
     return F
 
 
+def make_static_fields(spec, uniform_amp, smooth_amp, kmax=1, nmodes=6, seed=0):
+    """Static E and B for test-particle runs, shape (6, nz, ny, nx).
+
+    Each component is a random constant, uniform in [-uniform_amp,
+    uniform_amp], plus a smooth random part: nmodes plane waves with random
+    amplitude and phase whose wave numbers are whole multiples (at most
+    kmax) of the box's fundamental along each axis, scaled so that the part's
+    largest value on the grid is smooth_amp.  Either amplitude may be a pair
+    (for E, for B).  The values are taken at the grid indices (the field is
+    smooth, so the staggering does not matter)."""
+    def pair(v):
+        return (float(v[0]), float(v[1])) if isinstance(v, (tuple, list)) else (float(v), float(v))
+    uni, smo = pair(uniform_amp), pair(smooth_amp)
+    rng = np.random.default_rng(seed)
+    shape = grid_shape(spec)
+    nx, ny, nz = spec["n"]
+    dx, dy, dz = spec["d"]
+    x = (np.arange(nx) * dx)[None, None, :]
+    y = (np.arange(ny) * dy)[None, :, None]
+    z = (np.arange(shape[0]) * dz)[:, None, None]
+    L = (nx * dx, ny * dy, shape[0] * dz)
+    F = np.zeros((6,) + shape)
+    for c in range(6):
+        part = np.zeros(shape)
+        for _ in range(nmodes):
+            kv = [2.0 * math.pi / L[a] * rng.integers(-kmax, kmax + 1) for a in range(3)]
+            if spec["ndim"] == 2:
+                kv[2] = 0.0
+            phase = rng.uniform(0.0, 2.0 * math.pi)
+            part = part + rng.normal() * np.cos(kv[0] * x + kv[1] * y + kv[2] * z + phase)
+        peak = np.max(np.abs(part))
+        if smo[c // 3] > 0.0 and peak > 0.0:
+            F[c] += part * (smo[c // 3] / peak)
+        F[c] += uni[c // 3] * rng.uniform(-1.0, 1.0)
+    return F
+
+
 def make_state(spec, with_particles=True):
     """Everything the simulation starts from: particles per species and fields."""
     return {

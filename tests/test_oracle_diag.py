@@ -163,3 +163,39 @@ def test_store_fp32_rounds_the_stored_state_only():
         assert np.any(b.u[k] != b.u[k].astype(np.float32).astype(np.float64))
         # the rounding is a perturbation at float32 resolution, not a change of method
         assert np.max(np.abs(a.u[k] - b.u[k])) < 1e-5
+
+
+def test_store_fp32_cell_edge_tie_rule():
+    """The cell-edge reading for float32 offsets: cell = floor(x / dx) with the
+    offset in [0, 1); an offset that rounds up to 1 in float32 moves the
+    particle to the next cell (wrapping at the box edge) with offset 0.
+    Expected cells and offsets below are worked out by hand from the float32
+    neighbours of 1 (1 - 2^-24 and 1) and of 0."""
+    n = (32, 8, 1)
+    d = (0.3, 0.3, 1.0)
+    dt = 0.2
+    spec = {"ndim": 2, "n": n, "d": d, "dt": dt, "species": [{"Z": -1.0, "mu": 1.0, "a": 0.0}]}
+    ulp = 2.0 ** -24            # spacing of float32 values just below 1
+    top = 1.0 - ulp             # largest float32 offset below 1
+    # (start cell, start offset, displacement in cells) -> (end cell, end offset)
+    cases = [
+        (31, top, 0.75 * ulp, 0, 0.0),        # rounds up to 1 at the last cell: wraps to cell 0
+        (31, top, 0.25 * ulp, 31, top),       # rounds back to the top offset
+        (15, top, 0.75 * ulp, 16, 0.0),       # next cell (another 16-cell tile)
+        (0, 0.0, -0.25 * ulp, 0, 0.0),        # 1 - ulp/4 rounds to 1: stays at the edge of cell 0
+        (0, 0.0, -0.75 * ulp, 31, top),       # 1 - 3 ulp/4 rounds to 1 - ulp: previous cell (wrapped)
+        (16, 0.0, -0.75 * ulp, 15, top),
+        (7, top, 0.0, 7, top),                # at rest
+    ]
+    rows = []
+    for c, o, disp, _, _ in cases:
+        v = disp * d[0] / dt
+        u = v / np.sqrt(1.0 - v * v)
+        rows.append([(c + o) * d[0], 2.5 * d[1], 0.0, u, 0.0, 0.0, 0.0, 1.0, 0.0, 0.01])
+    state = {"particles": [np.array(rows)], "fields": np.zeros((6, 1, n[1], n[0]))}
+    sim = oracle.Sim(spec, state, test_particle=True, store_fp32=True)
+    sim.step(1)
+    xi = sim.xi[0][:, 0]
+    for q, (_, _, _, c1, o1) in enumerate(cases):
+        assert xi[q] == c1 + o1, (q, xi[q], c1 + o1)
+        assert 0.0 <= xi[q] < n[0]
