@@ -54,7 +54,27 @@ enum { PIC_ACC_DEFAULT = 0, PIC_ACC_FP32 = 1, PIC_ACC_FP64 = 2 };
 
 /* pic_config.flags */
 enum {
-    PIC_FLAG_TEST_PARTICLE = 1  /* fields frozen, no current deposit */
+    PIC_FLAG_TEST_PARTICLE = 1, /* fields frozen, no current deposit */
+    /* Deterministic mode: bitwise-reproducible runs.  The current of a step is
+     * summed as 64-bit fixed-point integers (units of 2^-S with S chosen at
+     * pic_init so that the sum of |Z w| over all particles stays below 2^61
+     * units: no node's current can pass it), inside each tile and across
+     * tiles, and converted to FP64 before the field update; the polarization
+     * of section 2 Eq. 4 is summed the same way (each spin component split in
+     * two 31-bit integer parts).  Integer sums do not depend on the order of
+     * the atomic additions, so two runs from the same state give bitwise
+     * identical particles, fields and polarization, and so does a run started
+     * again from pic_particles_cells and pic_fields (E, B) with
+     * PIC_FLAG_CELL_ROWS.  The FP64 current then carries a rounding of 2^-S per
+     * contribution instead of FP64 roundoff.  Not with pic_window and not in
+     * batches (PIC_EINVAL). */
+    PIC_FLAG_DETERMINISTIC = 2,
+    /* The initial particle rows of pic_state are in cell form,
+     * PIC_PARTICLE_CELL_COLS values: cell index along x, y, z (whole numbers,
+     * 0 <= c < n; 0 on axes beyond ndim), in-cell offset along x, y, z (in
+     * [0, 1); as pic_particles_cells returns them), ux uy uz, sx sy sz, w.
+     * This is how a run is restarted exactly from its read-back. */
+    PIC_FLAG_CELL_ROWS = 4
 };
 
 /* pic_fields mask bits; components are returned in this order */
@@ -68,6 +88,8 @@ enum {
 #define PIC_MAX_SPECIES 4
 #define PIC_PARTICLE_IN_COLS 10   /* x y z ux uy uz sx sy sz w */
 #define PIC_PARTICLE_OUT_COLS 11  /* id x y z ux uy uz sx sy sz w */
+#define PIC_PARTICLE_CELL_COLS 13      /* cx cy cz ox oy oz ux uy uz sx sy sz w */
+#define PIC_PARTICLE_CELL_OUT_COLS 14  /* id cx cy cz ox oy oz ux uy uz sx sy sz w */
 
 typedef struct {
     double Z;   /* charge in units of e (electron: -1) */
@@ -126,7 +148,10 @@ int pic_init(const pic_config* cfg, const pic_state* init, const pic_allocator* 
 
 /* Enqueue nsteps >= 0 full time steps.  Returns PIC_ESTATE on a NULL or
  * failed context, PIC_EHIP when a launch fails, PIC_ECAPACITY when particle
- * storage is exhausted. */
+ * storage is exhausted, PIC_ENONFINITE when the push has produced a NaN or
+ * infinite momentum or spin: every push kernel probes its particles and sets
+ * a device flag, which the host reads every 16 steps (when it waits for the
+ * stream anyway) and before every read-back call. */
 int pic_step(pic_ctx* ctx, int32_t nsteps);
 
 /* Section 2 Eq. 4: mean spin of the particles of one species (species = -1:
@@ -191,6 +216,24 @@ int pic_density(pic_ctx* ctx, int32_t species, double* out, size_t cap_doubles);
  * must hold count*11 values; *n_out receives the count.  Waits. */
 int pic_particles(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles,
                   int64_t* n_out);
+
+/* As pic_particles, with each position as the particle's cell index and its
+ * in-cell offset per axis, exactly as stored (rows of
+ * PIC_PARTICLE_CELL_OUT_COLS: id, cx cy cz, ox oy oz, ux uy uz, sx sy sz, w;
+ * 0 on axes beyond ndim).  Every value is the stored one converted to
+ * float64 without rounding, so that pic_init with PIC_FLAG_CELL_ROWS (the
+ * rows without the id column, in id order) restores the particles bit for
+ * bit.  cap_doubles must hold count*14 values.  Waits. */
+int pic_particles_cells(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles,
+                        int64_t* n_out);
+
+/* Test hook for the non-finite probe: overwrite u_x of one stored particle
+ * of `species` (the first one of the first non-empty tile) with a NaN.  The
+ * next pic_step's push then produces a non-finite state, which the probe in
+ * the push kernel records: pic_step returns PIC_ENONFINITE at its next check
+ * (every 16 steps) and the read-back calls return it at once.  Returns
+ * PIC_EINVAL when the species has no particle in a tile.  Waits. */
+int pic_test_poison(pic_ctx* ctx, int32_t species);
 
 /* Diagnostics in FP64: out[0 .. nspecies-1] kinetic energy per species
  * (sum mu (gamma-1) w V), out[nspecies] field energy (sum (E^2+B^2)/2 V),

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -81,6 +83,8 @@ struct Resolved {
     int nt[3];
     double slack;
     int use_acc64;
+    int det;         // PIC_FLAG_DETERMINISTIC: fixed-point current and polarization sums
+    int cell_rows;   // PIC_FLAG_CELL_ROWS: initial rows in cell form
 };
 
 template <typename real, typename acc_t>
@@ -125,7 +129,10 @@ Status resolve_config(const pic_config* cfg, const pic_state* init, Resolved& R)
         if (!(sp.mu > 0.0) || !std::isfinite(sp.mu) || !std::isfinite(sp.Z) || !std::isfinite(sp.a))
             return fail(PIC_EINVAL, "species %d: mass must be positive, Z and a finite", s);
     }
-    if (c.flags & ~PIC_FLAG_TEST_PARTICLE) return fail(PIC_EINVAL, "unknown flags 0x%x", c.flags);
+    if (c.flags & ~(PIC_FLAG_TEST_PARTICLE | PIC_FLAG_DETERMINISTIC | PIC_FLAG_CELL_ROWS))
+        return fail(PIC_EINVAL, "unknown flags 0x%x", c.flags);
+    R.det = (c.flags & PIC_FLAG_DETERMINISTIC) ? 1 : 0;
+    R.cell_rows = (c.flags & PIC_FLAG_CELL_ROWS) ? 1 : 0;
     if (c.deposit_acc < PIC_ACC_DEFAULT || c.deposit_acc > PIC_ACC_FP64)
         return fail(PIC_EINVAL, "unknown deposit_acc %d", c.deposit_acc);
     // FP64 shared-memory sums are the default: besides their precision, the
@@ -256,7 +263,8 @@ public:
     virtual Status step(int n) = 0;
     virtual Status polarization(int species, double emin, double emax, double P[3], int64_t* N) = 0;
     virtual Status fields(uint32_t mask, double* out, size_t cap) = 0;
-    virtual Status particles(int species, double* out, size_t cap, int64_t* n) = 0;
+    virtual Status particles(int species, double* out, size_t cap, int64_t* n, bool cells = false) = 0;
+    virtual Status poison(int species) = 0;
     virtual Status spectrum(int species, double emin, double emax, int nbins, double* count,
                             double* weight, double* spin) = 0;
     virtual Status spectrum_noalloc(int species, double emin, double emax, int nbins, double* count,
@@ -287,7 +295,8 @@ public:
     Status step(int n) override;
     Status polarization(int species, double emin, double emax, double P[3], int64_t* N) override;
     Status fields(uint32_t mask, double* out, size_t cap) override;
-    Status particles(int species, double* out, size_t cap, int64_t* n) override;
+    Status particles(int species, double* out, size_t cap, int64_t* n, bool cells = false) override;
+    Status poison(int species) override;
     Status spectrum(int species, double emin, double emax, int nbins, double* count, double* weight,
                     double* spin) override;
     Status spectrum_noalloc(int species, double emin, double emax, int nbins, double* count, double* weight,
@@ -327,14 +336,16 @@ private:
     void free_store(PArrays<real>& a);
     Status repack();
     Status check_lds() {
-        const size_t lds = use_acc64_ ? tile_lds_bytes<real, double>(g_, seg_.max_chunks)
-                                      : tile_lds_bytes<real, real>(g_, seg_.max_chunks);
+        // the deterministic mode's 64-bit integer sums take the room of FP64 ones
+        const size_t lds = (use_acc64_ || det_) ? tile_lds_bytes<real, double>(g_, seg_.max_chunks)
+                                                : tile_lds_bytes<real, real>(g_, seg_.max_chunks);
         if (lds > 64 * 1024)
             return fail(PIC_ECAPACITY, "a tile segment of %d slots needs %zu bytes of shared memory "
                         "(max 65536); use smaller tiles", seg_.max_chunks * 64, lds);
         return Status{};
     }
     Status reduce(int mode, const ReduceArgs& ra, double* host_acc);
+    Status nonfinite_flag(bool* set);
     Status spectrum_args(int species, double emin, double emax, int nbins, const double* count,
                          const double* weight, const double* spin, BinArgs& ba);
     Status compute_rho();
@@ -356,6 +367,10 @@ private:
     Consts<real> k_{};
     int deposit_ = 1;
     int use_acc64_ = 0;
+    int det_ = 0;                  // deterministic mode
+    int march_R_ = 1;              // 3D: tiles per z-run of the marching push (1: one tile per workgroup)
+    int march_xcd_ = 0;            // 3D marching push: contiguous range of runs per XCD
+    double fx_inv_ = 0.0;          // 1 / the fixed-point current's scale
     int nseg_ = 0;
     long long cap_total_ = 0;
     long long npart_ = 0;
@@ -462,6 +477,9 @@ static long long seg_capacity(long long count, double slack) {
 // particles, or any at all on a kStashPeriod boundary: overflow particles are
 // pushed from global memory at a fraction of the tile push's rate.
 constexpr int kStashCheck = 16;
+
+// Tiles per z-run of the 3D marching push.
+constexpr int kMarchRun = 8;
 constexpr int kStashPeriod = 64;
 constexpr long long kStashFrac = 512;
 constexpr int kStashBlocks = 1024;
@@ -514,6 +532,18 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     nseg_ = g_.ntiles * g_.nsp;
     deposit_ = (c.flags & PIC_FLAG_TEST_PARTICLE) ? 0 : 1;
     use_acc64_ = R.use_acc64;
+    det_ = R.det;
+    // 3D: the push marches along z over runs of kMarchRun tiles (overridable
+    // by SPINPIC_PUSH_RUN, 1 = one tile per workgroup, for measurements);
+    // it needs tiles of at least 3 cells along z
+    march_R_ = 1;
+    if (DIM == 3 && g_.T[2] >= 3) {
+        march_R_ = kMarchRun;
+        if (const char* e = std::getenv("SPINPIC_PUSH_RUN")) march_R_ = std::max(1, std::atoi(e));
+        if (const char* e = std::getenv("SPINPIC_PUSH_XCD")) march_xcd_ = std::atoi(e) != 0;
+    }
+    const int cols = R.cell_rows ? PIC_PARTICLE_CELL_COLS : PIC_PARTICLE_IN_COLS;
+    const int cu = R.cell_rows ? 6 : 3;   // column of ux (then s, then w)
 
     const double dt = c.dt;
     k_.dt = (real)dt;
@@ -551,6 +581,24 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
             pl.cell[a] = 0;
             pl.off[a] = 0.0;
         }
+        if (R.cell_rows) {
+            // cell index and offset as stored; an offset that rounds to 1 in
+            // the storage precision moves to the next cell (as in the push)
+            for (int a = 0; a < DIM; ++a) {
+                const double cf = row[a], off = row[3 + a];
+                if (!(cf >= 0.0 && cf < (double)g_.n[a] && cf == std::floor(cf))) return false;
+                if (!(off >= 0.0 && off < 1.0)) return false;
+                int ci = (int)cf;
+                double o = off;
+                if ((real)o >= real(1)) {
+                    o = 0.0;
+                    ci = (ci + 1) % g_.n[a];
+                }
+                pl.cell[a] = ci;
+                pl.off[a] = o;
+            }
+            return true;
+        }
         for (int a = 0; a < DIM; ++a) {
             const double xi = row[a] / d_[a];
             if (!std::isfinite(xi)) return false;
@@ -575,6 +623,7 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     // wavefront then sit in different cells, so their current deposits hit
     // different shared-memory words instead of serializing on one.
     const int tile_cells = g_.T[0] * g_.T[1] * g_.T[2];
+    double zw_sum = 0.0;   // sum of |Z w|: no node's current can exceed it
     std::vector<int32_t> segof((size_t)npart_);
     std::vector<uint32_t> key((size_t)npart_);
     {
@@ -582,17 +631,22 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         long long q = 0;
         for (int s = 0; s < c.nspecies; ++s) {
             const double* P = st ? st->particles[s] : nullptr;
+            const double Zs = std::fabs(c.sp[s].Z);
             for (long long i = 0; i < count_sp_[s]; ++i, ++q) {
-                const double* row = P + i * PIC_PARTICLE_IN_COLS;
-                for (int col = 0; col < PIC_PARTICLE_IN_COLS; ++col)
+                const double* row = P + i * cols;
+                for (int col = 0; col < cols; ++col)
                     if (!std::isfinite(row[col]))
                         return fail(PIC_EINVAL, "species %d particle %lld: non-finite input", s, i);
-                const double s2 = row[6] * row[6] + row[7] * row[7] + row[8] * row[8];
+                const double* sv = row + cu + 3;
+                const double s2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
                 if (std::fabs(s2 - 1.0) > 1e-6)
                     return fail(PIC_EINVAL, "species %d particle %lld: |s| = %.9f, must be 1", s, i,
                                 std::sqrt(s2));
+                zw_sum += Zs * std::fabs((double)(real)row[cu + 6]);
                 Placed pl;
-                place(row, pl);
+                if (!place(row, pl))
+                    return fail(PIC_EINVAL, "species %d particle %lld: cell outside 0..n-1 or offset outside [0, 1)",
+                                s, i);
                 const int sid = tile_of(pl) * c.nspecies + s;
                 segof[q] = sid;
                 count[sid]++;
@@ -605,6 +659,17 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
                 key[q] = (uint32_t)k64;
             }
         }
+    }
+    // Deterministic mode: fixed-point unit 2^-S with the largest S for which
+    // zw_sum, a bound on every node's current, stays below 2^61 units
+    k_.fx_scale = 0.0;
+    fx_inv_ = 0.0;
+    if (det_) {
+        int e = 0;
+        if (zw_sum > 0.0) (void)std::frexp(zw_sum, &e);   // zw_sum < 2^e
+        const int S = 61 - e;
+        k_.fx_scale = std::ldexp(1.0, S);
+        fx_inv_ = std::ldexp(1.0, -S);
     }
     std::vector<int32_t> h_start(nseg_), h_cap(nseg_), h_count(nseg_);
     cap_total_ = 0;
@@ -698,17 +763,17 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
                 for (long long m = first[sg]; m < first[sg + 1]; ++m) {
                     const long long q = perm[m];
                     const long long i = q - spbase[s];
-                    const double* row = P + i * PIC_PARTICLE_IN_COLS;
+                    const double* row = P + i * cols;
                     Placed pl;
                     place(row, pl);
                     const long long slot = h_start[sg] + fill[sg]++;
                     hcell[slot] = pack_cell<DIM>(pl.cell[0], pl.cell[1], pl.cell[2]);
                     for (int a = 0; a < DIM; ++a) hoff[a][slot] = (real)pl.off[a];
                     for (int a = 0; a < 3; ++a) {
-                        hu[a][slot] = (real)row[3 + a];
-                        hs[a][slot] = (real)row[6 + a];
+                        hu[a][slot] = (real)row[cu + a];
+                        hs[a][slot] = (real)row[cu + 3 + a];
                     }
-                    hw[slot] = (real)row[9];
+                    hw[slot] = (real)row[cu + 6];
                     hid[slot] = (int32_t)i;
                 }
             }
@@ -774,6 +839,9 @@ Status Engine<real, DIM>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
         if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
             HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            if (h_ctr_[CTR_NONFINITE])
+                return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin before step %lld",
+                            (long long)nstep_);
             if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
                 Status S = repack();
                 if (S.code) return S;
@@ -785,13 +853,29 @@ Status Engine<real, DIM>::step(int nsteps) {
         const int jnext = jcur_ ^ 1;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jnext][a];
         tstart(0);
-        if (use_acc64_)
+        if (march_R_ > 1) {
+            if (det_)
+                HIP_OR_FAIL((launch_push_march<real, unsigned long long>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_,
+                                                                         march_R_, march_xcd_, stream_)));
+            else if (use_acc64_)
+                HIP_OR_FAIL((launch_push_march<real, double>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, march_R_,
+                                                             march_xcd_, stream_)));
+            else
+                HIP_OR_FAIL((launch_push_march<real, real>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, march_R_,
+                                                           march_xcd_, stream_)));
+        } else if (det_) {
+            HIP_OR_FAIL((launch_push_tiles<real, unsigned long long, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_,
+                                                                          stream_)));
+        } else if (use_acc64_) {
             HIP_OR_FAIL((launch_push_tiles<real, double, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
-        else
+        } else {
             HIP_OR_FAIL((launch_push_tiles<real, real, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
+        }
         tstop(0);
         tstart(1);
         HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, kStashBlocks, stream_)));
+        // the deterministic mode's fixed-point current becomes FP64 for the field update
+        if (det_ && deposit_) HIP_OR_FAIL(launch_fixed_to_double(f_.J, g_.ncells, fx_inv_, stream_));
         tstop(1);
         tstart(2);
         HIP_OR_FAIL((launch_insert<real, DIM>(g_, p_, seg_, lv_, st_, ctr_, slot, moved_, 1024, stream_)));
@@ -817,7 +901,7 @@ Status Engine<real, DIM>::step(int nsteps) {
         // the overflow count for the next check (read only there: a copy
         // every step would cost a transfer and two launch gaps per step)
         if ((nstep_ + 1) % kStashCheck == 0)
-            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
+            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, 2 * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
@@ -916,6 +1000,15 @@ Status Engine<real, DIM>::reduce(int mode, const ReduceArgs& ra, double* host_ac
     return Status{};
 }
 
+// The push kernels' non-finite flag, read now (waits for the stream).
+template <typename real, int DIM>
+Status Engine<real, DIM>::nonfinite_flag(bool* set) {
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    HIP_OR_FAIL(hipMemcpy(h_ctr_ + CTR_NONFINITE, ctr_ + CTR_NONFINITE, sizeof(int32_t), hipMemcpyDeviceToHost));
+    *set = h_ctr_[CTR_NONFINITE] != 0;
+    return Status{};
+}
+
 template <typename real, int DIM>
 Status Engine<real, DIM>::compute_rho() {
     ReduceArgs ra{};
@@ -941,12 +1034,32 @@ Status Engine<real, DIM>::polarization(int species, double emin, double emax, do
         ra.mu[s] = s < g_.nsp ? R_.cfg.sp[s].mu : 1.0;
         ra.Z[s] = s < g_.nsp ? R_.cfg.sp[s].Z : 0.0;
     }
-    double acc[8];
-    Status S = reduce(RED_POLARIZATION, ra, acc);
+    bool bad = false;
+    Status S = nonfinite_flag(&bad);
     if (S.code) return S;
-    const double n = acc[3];
-    *N = (int64_t)std::llround(n);
-    for (int a = 0; a < 3; ++a) P[a] = n > 0 ? acc[a] / n : 0.0;
+    if (bad) return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin");
+    if (det_) {
+        // integer sums of the two 31-bit parts of every spin component
+        unsigned long long acc[8];
+        HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+        HIP_OR_FAIL((launch_polarization_fixed<real, DIM>(g_, p_, seg_, st_, ctr_, ra,
+                                                          reinterpret_cast<unsigned long long*>(acc_), stream_)));
+        HIP_OR_FAIL(hipMemcpyAsync(acc, acc_, 8 * sizeof(double), hipMemcpyDeviceToHost, stream_));
+        HIP_OR_FAIL(hipStreamSynchronize(stream_));
+        const long long n = (long long)acc[6];
+        *N = n;
+        for (int a = 0; a < 3; ++a) {
+            const double sum = ((double)(long long)acc[a] + (double)(long long)acc[3 + a] * 0x1p-31) * 0x1p-31;
+            P[a] = n > 0 ? sum / (double)n : 0.0;
+        }
+    } else {
+        double acc[8];
+        S = reduce(RED_POLARIZATION, ra, acc);
+        if (S.code) return S;
+        const double n = acc[3];
+        *N = (int64_t)std::llround(n);
+        for (int a = 0; a < 3; ++a) P[a] = n > 0 ? acc[a] / n : 0.0;
+    }
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(P[a])) return fail(PIC_ENONFINITE, "polarization is not finite");
     return Status{};
@@ -1101,14 +1214,17 @@ Status Engine<real, DIM>::fields(uint32_t mask, double* out, size_t cap) {
 }
 
 template <typename real, int DIM>
-Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_t* n_out) {
+Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_t* n_out, bool cells) {
     if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
     long long per[kMaxSpecies];
     Status L = live_counts(per);
     if (L.code) return L;
     const long long n = per[species];
     if (n_out) *n_out = n;
-    if (cap < (size_t)n * PIC_PARTICLE_OUT_COLS) return fail(PIC_EINVAL, "cap too small for %lld particles", n);
+    // rows: id, position (x y z, or cell index and offset per axis), u, s, w
+    const int ncol = cells ? PIC_PARTICLE_CELL_OUT_COLS : PIC_PARTICLE_OUT_COLS;
+    const int cu = cells ? 7 : 4;
+    if (cap < (size_t)n * ncol) return fail(PIC_EINVAL, "cap too small for %lld particles", n);
     if (n > 0 && !out) return fail(PIC_EINVAL, "host_out is NULL");
     // Without a moving window the ids are 0 .. n-1 and row i is particle i;
     // with one, the rows are gathered first and sorted by id.
@@ -1116,7 +1232,7 @@ Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_
     std::vector<double> rows;
     std::vector<long long> ids;
     if (!by_index) {
-        rows.resize((size_t)n * PIC_PARTICLE_OUT_COLS);
+        rows.resize((size_t)n * ncol);
         ids.reserve((size_t)n);
     }
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
@@ -1157,21 +1273,28 @@ Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_
                 if (by_index) {
                     if (i < 0 || i >= n || seen[i]) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (id %lld)", i);
                     seen[i] = 1;
-                    row = out + i * PIC_PARTICLE_OUT_COLS;
+                    row = out + i * ncol;
                 } else {
                     if ((long long)ids.size() >= n) return fail(PIC_ESTATE, "particle bookkeeping is corrupt (count)");
-                    row = rows.data() + ids.size() * PIC_PARTICLE_OUT_COLS;
+                    row = rows.data() + ids.size() * ncol;
                     ids.push_back(i);
                 }
                 int c[3];
                 unpack_cell<DIM>(cell[q], c[0], c[1], c[2]);
                 row[0] = (double)i;
-                for (int a = 0; a < 3; ++a) row[1 + a] = a < DIM ? ((double)c[a] + (double)off[a][q]) * d_[a] : 0.0;
-                for (int a = 0; a < 3; ++a) {
-                    row[4 + a] = (double)u[a][q];
-                    row[7 + a] = (double)s[a][q];
+                if (cells) {
+                    for (int a = 0; a < 3; ++a) {
+                        row[1 + a] = a < DIM ? (double)c[a] : 0.0;
+                        row[4 + a] = a < DIM ? (double)off[a][q] : 0.0;
+                    }
+                } else {
+                    for (int a = 0; a < 3; ++a) row[1 + a] = a < DIM ? ((double)c[a] + (double)off[a][q]) * d_[a] : 0.0;
                 }
-                row[10] = (double)w[q];
+                for (int a = 0; a < 3; ++a) {
+                    row[cu + a] = (double)u[a][q];
+                    row[cu + 3 + a] = (double)s[a][q];
+                }
+                row[cu + 6] = (double)w[q];
             }
         return Status{};
     };
@@ -1196,10 +1319,29 @@ Status Engine<real, DIM>::particles(int species, double* out, size_t cap, int64_
     for (long long q = 0; q < n; ++q) {
         if (q > 0 && ids[order[q]] == ids[order[q - 1]])
             return fail(PIC_ESTATE, "particle id %lld appears twice", ids[order[q]]);
-        std::memcpy(out + q * PIC_PARTICLE_OUT_COLS, rows.data() + order[q] * PIC_PARTICLE_OUT_COLS,
-                    PIC_PARTICLE_OUT_COLS * sizeof(double));
+        std::memcpy(out + q * ncol, rows.data() + order[q] * ncol, ncol * sizeof(double));
     }
     return Status{};
+}
+
+// Test hook: a NaN into u_x of the first particle of the first tile that
+// holds one of this species.
+template <typename real, int DIM>
+Status Engine<real, DIM>::poison(int species) {
+    if (species < 0 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    std::vector<int32_t> start(nseg_), count(nseg_);
+    HIP_OR_FAIL(hipMemcpy(start.data(), seg_.start, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(hipMemcpy(count.data(), seg_.count, nseg_ * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int t = 0; t < g_.ntiles; ++t) {
+        const int sid = t * g_.nsp + species;
+        if (count[sid] > 0) {
+            const real nan = std::numeric_limits<real>::quiet_NaN();
+            HIP_OR_FAIL(hipMemcpy(p_.u[0] + start[sid], &nan, sizeof(real), hipMemcpyHostToDevice));
+            return Status{};
+        }
+    }
+    return fail(PIC_EINVAL, "species %d has no particle in a tile", species);
 }
 
 template <typename real, int DIM>
@@ -1328,6 +1470,7 @@ Status Engine<real, DIM>::grow_stores(long long need) {
 template <typename real, int DIM>
 Status Engine<real, DIM>::window(const pic_window_config* w) {
     if (!w) return fail(PIC_EINVAL, "window config is NULL");
+    if (det_) return fail(PIC_EINVAL, "the moving window is not available in the deterministic mode");
     if (!(w->speed >= 0.0) || !std::isfinite(w->speed)) return fail(PIC_EINVAL, "window speed must be >= 0");
     if (w->shift_cells < 1 || w->shift_cells >= g_.n[0] || w->shift_cells % g_.T[0] != 0)
         return fail(PIC_EINVAL, "shift_cells = %d must be a multiple of the tile's x edge %d and below n[0] = %d",
@@ -1951,6 +2094,9 @@ Status BatchEngine<real>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
         if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
             HIP_OR_FAIL(hipStreamSynchronize(stream_));
+            if (h_ctr_[CTR_NONFINITE])
+                return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin before step %lld",
+                            (long long)nstep_);
             if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
                 Status S = repack();
                 if (S.code) return S;
@@ -1991,7 +2137,7 @@ Status BatchEngine<real>::step(int nsteps) {
         }
         // the overflow count for the next check only
         if ((nstep_ + 1) % kStashCheck == 0)
-            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, sizeof(int32_t),
+            HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, 2 * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
@@ -2338,6 +2484,16 @@ int pic_particles(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_do
     return finish(ctx, ctx->eng->particles(species, host_out, cap_doubles, n_out));
 }
 
+int pic_particles_cells(pic_ctx* ctx, int32_t species, double* host_out, size_t cap_doubles, int64_t* n_out) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->particles(species, host_out, cap_doubles, n_out, true));
+}
+
+int pic_test_poison(pic_ctx* ctx, int32_t species) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->poison(species));
+}
+
 int pic_energy(pic_ctx* ctx, double* out, int32_t cap) {
     CTX_CHECK(ctx);
     return finish(ctx, ctx->eng->energy(out, cap));
@@ -2399,6 +2555,8 @@ Status batch_resolve(int32_t nrun, const pic_config* cfgs, const pic_state* init
         const pic_config& c = cfgs[r];
         const pic_config& c0 = cfgs[0];
         if (c.ndim != 2) return fail(PIC_EINVAL, "run %d: batches hold 2D runs only", r);
+        if (c.flags & (PIC_FLAG_DETERMINISTIC | PIC_FLAG_CELL_ROWS))
+            return fail(PIC_EINVAL, "run %d: the deterministic mode and cell rows are not available in batches", r);
         bool same = c.precision == c0.precision && c.nspecies == c0.nspecies && c.flags == c0.flags &&
                     c.deposit_acc == c0.deposit_acc && Rs[r].slack == Rs[0].slack;
         for (int s = 0; s < c.nspecies && same; ++s)

@@ -529,6 +529,110 @@ k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st
     if (mode != RED_RHO) block_sum_add<4>(v, acc);
 }
 
+// ---- deterministic mode
+
+// A spin component s (|s| <= 1) as two integers: s = (hi + lo 2^-31) 2^-31,
+// hi = floor(s 2^31), lo = rint((s 2^31 - hi) 2^31), exact to 2^-62.  Sums of
+// the integers are exact, so they do not depend on the order of the adds.
+__device__ inline void split31(double s, long long& hi, long long& lo) {
+    const double x = s * 2147483648.0;
+    const double h = floor(x);
+    hi = (long long)h;
+    lo = __double2ll_rn((x - h) * 2147483648.0);
+}
+
+__device__ inline long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    return v;
+}
+
+// Section 2 Eq. 4 in the deterministic mode: over the selected particles
+// acc[k] += hi(s_k), acc[3 + k] += lo(s_k) (k = 0..2), acc[6] += 1, all as
+// 64-bit integers; the selection is the one of RED_POLARIZATION.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_polarization_fixed(Geom g, PArrays<real> p, Segs seg, PArrays<real> st, const int32_t* __restrict__ ctr,
+                     ReduceArgs ra, unsigned long long* acc, int nseg) {
+    long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+    auto one = [&](const PArrays<real>& A, long long i, int sp) {
+        if (ra.species >= 0 && sp != ra.species) return;
+        const double ux = A.u[0][i], uy = A.u[1][i], uz = A.u[2][i];
+        const double gamma = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        const double ek = ra.mu[sp] * (gamma - 1.0) * kMeC2MeV;
+        if (!(ek >= ra.emin && ek < ra.emax)) return;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            long long h, l;
+            split31((double)A.s[k][i], h, l);
+            v[k] += h;
+            v[3 + k] += l;
+        }
+        v[6] += 1;
+    };
+    if ((int)blockIdx.x < nseg) {
+        const int sid = blockIdx.x;
+        const int sp = sid % g.nsp;
+        const long long start = seg.start[sid];
+        const int n = seg.count[sid];
+        for (int i = threadIdx.x; i < n; i += kBlock) one(p, start + i, sp);
+    } else {
+        const int n = ctr[CTR_STASH];
+        const int b = blockIdx.x - nseg, nb = gridDim.x - nseg;
+        for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) {
+            if (st.cell[i] == kDeadCell) continue;
+            const int tag = st.sp[i];
+            if (tag / kMaxSpecies != ra.run) continue;
+            one(st, i, tag % kMaxSpecies);
+        }
+    }
+    __shared__ long long part[kBlock / 64][7];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = wave_sum_ll(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) part[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        long long t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w][threadIdx.x];
+        if (t != 0) atomicAdd(acc + threadIdx.x, (unsigned long long)t);
+    }
+}
+
+// The deterministic mode's current: each J word holds a fixed-point integer
+// (units of 1/scale) during the push; here it becomes its FP64 value, in place.
+__global__ void __launch_bounds__(kBlock)
+k_fixed_to_double(double* __restrict__ J0, double* __restrict__ J1, double* __restrict__ J2, long long n,
+                  double inv_scale) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) {
+        J0[i] = (double)__double_as_longlong(J0[i]) * inv_scale;
+        J1[i] = (double)__double_as_longlong(J1[i]) * inv_scale;
+        J2[i] = (double)__double_as_longlong(J2[i]) * inv_scale;
+    }
+}
+
+hipError_t launch_fixed_to_double(double* const J[3], long long n, double inv_scale, hipStream_t stream) {
+    long long blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fixed_to_double, dim3((unsigned)blocks), dim3(kBlock), 0, stream, J[0], J[1], J[2], n,
+                       inv_scale);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM>
+hipError_t launch_polarization_fixed(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
+                                     const int32_t* ctr, const ReduceArgs& ra, unsigned long long* acc,
+                                     hipStream_t stream) {
+    const int nseg = g.ntiles * g.nsp;
+    hipLaunchKernelGGL((k_polarization_fixed<real, DIM>), dim3(nseg + 64), dim3(kBlock), 0, stream, g, p, seg, st,
+                       ctr, ra, acc, nseg);
+    return hipGetLastError();
+}
+
 // Bin of v among n equal bins over [lo, hi), or -1 outside.  The energy and
 // bin arithmetic is written out without contraction into fused multiply-adds,
 // so that bin decisions are reproducible from the particle values alone.
@@ -826,7 +930,9 @@ hipError_t launch_fill_zero(double* out, long long n, hipStream_t stream) {
         const PArrays<real>&, const Segs&, const PArrays<real>&, const int32_t*,               \
         const ReduceArgs&, double*, double*, hipStream_t);                                      \
     template hipError_t launch_bin_particles<real, DIM>(const Geom&, const PArrays<real>&,     \
-        const Segs&, const PArrays<real>&, const int32_t*, const BinArgs&, double*, hipStream_t);
+        const Segs&, const PArrays<real>&, const int32_t*, const BinArgs&, double*, hipStream_t); \
+    template hipError_t launch_polarization_fixed<real, DIM>(const Geom&, const PArrays<real>&, \
+        const Segs&, const PArrays<real>&, const int32_t*, const ReduceArgs&, unsigned long long*, hipStream_t);
 
 SPINPIC_INST_GRID(2)
 SPINPIC_INST_GRID(3)

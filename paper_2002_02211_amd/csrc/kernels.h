@@ -15,9 +15,16 @@ hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays
                              const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
                              const Fields<freal>& f, int deposit, hipStream_t stream);
 
+// 3D push marching along z over runs of R tiles of one tile column (field
+// and current guard planes carried between the tiles of a run); T[2] >= 3.
+template <typename real, typename acc_t>
+hipError_t launch_push_march(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
+                             const PArrays<real>& lv, int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
+                             int R, int xcd_major, hipStream_t stream);
+
 template <typename real, int DIM>
 hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
-                             const int32_t* ctr, const Fields<freal>& f, int deposit, int blocks,
+                             int32_t* ctr, const Fields<freal>& f, int deposit, int blocks,
                              hipStream_t stream);
 
 template <typename real, int DIM>
@@ -68,7 +75,7 @@ hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* ord
 template <typename real, typename acc_t>
 int push_batch_blocks_per_cu(size_t lds);
 template <typename real>
-hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, const int32_t* ctr,
+hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, int32_t* ctr,
                                    const Fields<freal>& f, int deposit, int blocks, hipStream_t stream);
 template <typename real>
 hipError_t launch_insert_batch(const RunDesc<real>* runs, const PArrays<real>& p, const Segs& seg,
@@ -185,6 +192,16 @@ template <typename real, int DIM>
 hipError_t launch_div_residual(const Geom& g, const Vec3d& inv_d,
                                const Fields<real>& f, const double* rho, const double* ref,
                                double* ref_out, double* blockmax, int blocks, hipStream_t stream);
+
+// Deterministic mode.  Section 2 Eq. 4 summed as integers: acc[k] += hi,
+// acc[3 + k] += lo of each selected s_k (s_k = (hi + lo 2^-31) 2^-31), acc[6]
+// += 1; acc must be zeroed first.  And the current's fixed-point words
+// turned into their FP64 values in place (value = integer * inv_scale).
+template <typename real, int DIM>
+hipError_t launch_polarization_fixed(const Geom& g, const PArrays<real>& p, const Segs& seg, const PArrays<real>& st,
+                                     const int32_t* ctr, const ReduceArgs& ra, unsigned long long* acc,
+                                     hipStream_t stream);
+hipError_t launch_fixed_to_double(double* const J[3], long long n, double inv_scale, hipStream_t stream);
 
 // out[0 .. n) = 0 (a kernel, not a memset).
 hipError_t launch_fill_zero(double* out, long long n, hipStream_t stream);

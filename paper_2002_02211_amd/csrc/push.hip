@@ -115,10 +115,18 @@ __device__ inline void copy_particle(const PArrays<real>& from, long long i, con
 // run the tile belongs to; its segments are sid_base + t nsp + sp, and its
 // leavers carry inst_tag + sp in the leaver store's species word.  Every
 // thread of the workgroup must call it.
+// In a z-march (3D, see k_push_march), consecutive tiles of one column share
+// guard planes: fz0 = 2 when the first two field planes (local z = -1, 0)
+// were carried over from the previous tile and only the others are staged
+// (0: stage all); jz0 = 3 when the first three current planes hold the
+// previous tile's carried sums and only the others start at zero; jkeep = 3
+// when the last three current planes (local z = T-1 .. T+1) are kept in
+// shared memory for the next tile instead of being added to global J.
 template <typename real, typename acc_t, int DIM>
 __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
                           const PArrays<real>& lv, int32_t* __restrict__ ctr, int slot, const Fields<freal>& f,
-                          int deposit, int t, int sid_base, int inst_tag) {
+                          int deposit, int t, int sid_base, int inst_tag, int fz0 = 0, int jz0 = 0,
+                          int jkeep = 0) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_nleave, s_lbase;
     int tc[3];
@@ -180,7 +188,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
         const bool xin = !g.open_x || (org[0] - 1 + gx >= 0 && org[0] - 1 + gx < g.n[0]);
         const int rows = Gy * Gz;
         if (r0 < rpp) {
-            for (int rb = r0; rb < rows; rb += kStageRows * rpp) {
+            for (int rb = fz0 * Gy + r0; rb < rows; rb += kStageRows * rpp) {
                 freal v[kStageRows][6];
 #pragma unroll
                 for (int q = 0; q < kStageRows; ++q) {
@@ -209,8 +217,17 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
             }
         }
     }
-    if (deposit)
-        for (int idx = threadIdx.x; idx < 3 * H; idx += kBlock) Jl[idx] = acc_t(0);
+    if (deposit) {
+        if (jz0 == 0) {
+            for (int idx = threadIdx.x; idx < 3 * H; idx += kBlock) Jl[idx] = acc_t(0);
+        } else {
+            const int per = H - jz0 * Hxy;   // per component, from plane jz0 on
+            for (int idx = threadIdx.x; idx < 3 * per; idx += kBlock) {
+                const int c = idx / per;
+                Jl[c * H + jz0 * Hxy + (idx - c * per)] = acc_t(0);
+            }
+        }
+    }
     __syncthreads();
 
     const TileFields<real, DIM> TF{F, Gx, Gxy, G};
@@ -419,7 +436,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
         // current beyond an open x face is dropped
         const bool xin = !g.open_x || (org[0] - 1 + hx >= 0 && org[0] - 1 + hx < g.n[0]);
         if (r0 < rpp && xin) {
-            for (int hz = 0; hz < Hz; ++hz) {
+            for (int hz = 0; hz < Hz - jkeep; ++hz) {
                 const long long iz = DIM == 3 ? wrap_near(org[2] - 1 + hz, g.n[2]) : 0;
                 for (int hy = r0; hy < Hy; hy += rpp) {
                     const long long iy = wrap_near(org[1] - 1 + hy, g.n[1]);
@@ -456,15 +473,72 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     push_tile<real, acc_t, DIM>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0);
 }
 
+// 3D push marching along z: workgroup w takes a run of up to R tiles of one
+// (x, y) tile column, z tile rz R .. rz R + R - 1, and pushes them in order.
+// Between two tiles of a run the field planes at local z = T-1, T (the next
+// tile's guard planes -1, 0) stay in shared memory, and the current planes
+// at local z = T-1 .. T+1 (the next tile's -1 .. 1) carry their sums over
+// instead of being added to global J; the next tile then stages T new field
+// planes instead of T + 2 and the run adds T current planes per tile to
+// global J instead of T + 3.  Needs T[2] >= 3 (the carried planes and their
+// destinations do not overlap).  Runs are numbered x fastest, then y, then
+// z; with xcd_major the runs of XCD x (workgroups x, x + 8, ...) are one
+// contiguous range of that order, else they go in launch order.
+template <typename real, typename acc_t>
+__global__ void __launch_bounds__(kBlock)
+k_push_march(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv, int32_t* __restrict__ ctr,
+             int slot, Fields<freal> f, int deposit, int R, int nruns, int xcd_major) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
+    int item = (int)blockIdx.x;
+    if (xcd_major) {
+        const int per = (nruns + 7) >> 3;
+        item = (item & 7) * per + (item >> 3);
+    }
+    if (item >= nruns) return;
+    const int tx = item % g.nt[0];
+    const int ty = (item / g.nt[0]) % g.nt[1];
+    const int rz = item / (g.nt[0] * g.nt[1]);
+    const int z0 = rz * R, z1 = min(g.nt[2], z0 + R);
+    const int T2 = g.T[2];
+    const int Gx = g.T[0] + 2, Gy = g.T[1] + 2, Gz = T2 + 2;
+    const int Gxy = Gx * Gy, G = Gxy * Gz;
+    const int Hx = g.T[0] + 3, Hy = g.T[1] + 3, Hz = T2 + 3;
+    const int Hxy = Hx * Hy, H = Hxy * Hz;
+    real* F = reinterpret_cast<real*>(smem);
+    acc_t* Jl = reinterpret_cast<acc_t*>(smem + align16((size_t)6 * G * sizeof(real)));
+    for (int tz = z0; tz < z1; ++tz) {
+        const bool first = tz == z0, last = tz == z1 - 1;
+        if (!first) {
+            // carry: field planes T, T + 1 -> 0, 1; current planes T .. T + 2 -> 0 .. 2
+            for (int idx = threadIdx.x; idx < 6 * 2 * Gxy; idx += kBlock) {
+                const int c = idx / (2 * Gxy), r = idx - c * 2 * Gxy;
+                F[c * G + r] = F[c * G + T2 * Gxy + r];
+            }
+            if (deposit)
+                for (int idx = threadIdx.x; idx < 3 * 3 * Hxy; idx += kBlock) {
+                    const int c = idx / (3 * Hxy), r = idx - c * 3 * Hxy;
+                    Jl[c * H + r] = Jl[c * H + T2 * Hxy + r];
+                }
+            __syncthreads();
+        }
+        const int t = tx + g.nt[0] * (ty + g.nt[1] * tz);
+        push_tile<real, acc_t, 3>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0, first ? 0 : 2, first ? 0 : 3,
+                                  last ? 0 : 3);
+        __syncthreads();   // the carried planes are read by the next tile's setup
+    }
+}
+
 // Particles in the overflow store (tiles that ran out of slots): the same
 // step, gathering from and depositing into global memory directly.
 // One particle of the overflow store (species sp): gather from and deposit
 // into the global fields of its run.
+// Returns true when the pushed momentum or spin is not finite.
 template <typename real, int DIM>
-__device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, const PArrays<real>& st, int i,
+__device__ inline bool push_stash_one(const Geom& g, const Consts<real>& k, const PArrays<real>& st, int i,
                                       int sp, const Fields<freal>& f, int deposit) {
     const int32_t cell = st.cell[i];
-    if (cell == kDeadCell) return;   // left the box earlier
+    if (cell == kDeadCell) return false;   // left the box earlier
     GlobalFields<freal, DIM> GF;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -540,15 +614,18 @@ __device__ inline void push_stash_one(const Geom& g, const Consts<real>& k, cons
         st.u[a][i] = u[a];
         st.s[a][i] = s[a];
     }
+    return !__builtin_isfinite(dot3(u, u) + dot3(s, s));
 }
 
 template <typename real, int DIM>
 __global__ void __launch_bounds__(kBlock)
-k_push_stash(Geom g, Consts<real> k, PArrays<real> st, const int32_t* __restrict__ ctr,
+k_push_stash(Geom g, Consts<real> k, PArrays<real> st, int32_t* __restrict__ ctr,
              Fields<freal> f, int deposit) {
     const int n = ctr[CTR_STASH];
+    bool bad = false;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-        push_stash_one<real, DIM>(g, k, st, i, st.sp[i], f, deposit);
+        bad = push_stash_one<real, DIM>(g, k, st, i, st.sp[i], f, deposit) || bad;
+    if (bad) ctr[CTR_NONFINITE] = 1;
 }
 
 // Positions for the active lanes of a wavefront that each add 1 to
@@ -691,15 +768,17 @@ k_push_tiles_batch(const RunDesc<real>* __restrict__ runs, const TileRef* __rest
 
 template <typename real>
 __global__ void __launch_bounds__(kBlock)
-k_push_stash_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> st, const int32_t* __restrict__ ctr,
+k_push_stash_batch(const RunDesc<real>* __restrict__ runs, PArrays<real> st, int32_t* __restrict__ ctr,
                    Fields<freal> f, int deposit) {
     const int n = ctr[CTR_STASH];
+    bool bad = false;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int tag = st.sp[i];
         const int run = tag / kMaxSpecies;
-        push_stash_one<real, 2>(runs[run].g, runs[run].k, st, i, tag - run * kMaxSpecies,
-                                run_fields<real>(f, runs[run].cell_off), deposit);
+        bad = push_stash_one<real, 2>(runs[run].g, runs[run].k, st, i, tag - run * kMaxSpecies,
+                                      run_fields<real>(f, runs[run].cell_off), deposit) || bad;
     }
+    if (bad) ctr[CTR_NONFINITE] = 1;
 }
 
 // The batch's leavers (the list [0, ctr[slot]) of the leaver store): each
@@ -895,9 +974,22 @@ hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays
     return hipGetLastError();
 }
 
+template <typename real, typename acc_t>
+hipError_t launch_push_march(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
+                             const PArrays<real>& lv, int32_t* ctr, int slot, const Fields<freal>& f, int deposit,
+                             int R, int xcd_major, hipStream_t stream) {
+    if (g.ndim != 3 || g.T[2] < 3 || R < 1) return hipErrorInvalidValue;
+    const size_t lds = tile_lds_bytes<real, acc_t>(g, seg.max_chunks);
+    const int nruns = g.nt[0] * g.nt[1] * ((g.nt[2] + R - 1) / R);
+    const int grid = ((nruns + 7) >> 3) * 8;
+    hipLaunchKernelGGL((k_push_march<real, acc_t>), dim3(grid), dim3(kBlock), lds, stream, g, k, p, seg, lv, ctr,
+                       slot, f, deposit, R, nruns, xcd_major);
+    return hipGetLastError();
+}
+
 template <typename real, int DIM>
 hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
-                             const int32_t* ctr, const Fields<freal>& f, int deposit,
+                             int32_t* ctr, const Fields<freal>& f, int deposit,
                              int blocks, hipStream_t stream) {
     hipLaunchKernelGGL((k_push_stash<real, DIM>), dim3(blocks), dim3(kBlock), 0, stream,
                        g, k, st, ctr, f, deposit);
@@ -924,7 +1016,7 @@ hipError_t launch_push_tiles_batch(const RunDesc<real>* runs, const TileRef* ord
 }
 
 template <typename real>
-hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, const int32_t* ctr,
+hipError_t launch_push_stash_batch(const RunDesc<real>* runs, const PArrays<real>& st, int32_t* ctr,
                                    const Fields<freal>& f, int deposit, int blocks, hipStream_t stream) {
     hipLaunchKernelGGL((k_push_stash_batch<real>), dim3(blocks), dim3(kBlock), 0, stream, runs, st, ctr, f,
                        deposit);
@@ -960,10 +1052,10 @@ template hipError_t launch_push_tiles_batch<float, float>(const RunDesc<float>*,
 template hipError_t launch_push_tiles_batch<double, double>(const RunDesc<double>*, const TileRef*, const XcdQueues&, int,
     size_t, const PArrays<double>&, const Segs&, const PArrays<double>&, int32_t*, int, const Fields<freal>&,
     int, unsigned long long*, hipStream_t);
-template hipError_t launch_push_stash_batch<float>(const RunDesc<float>*, const PArrays<float>&, const int32_t*,
+template hipError_t launch_push_stash_batch<float>(const RunDesc<float>*, const PArrays<float>&, int32_t*,
     const Fields<freal>&, int, int, hipStream_t);
 template hipError_t launch_push_stash_batch<double>(const RunDesc<double>*, const PArrays<double>&,
-    const int32_t*, const Fields<freal>&, int, int, hipStream_t);
+    int32_t*, const Fields<freal>&, int, int, hipStream_t);
 template hipError_t launch_insert_batch<float>(const RunDesc<float>*, const PArrays<float>&, const Segs&,
     const PArrays<float>&, const PArrays<float>&, int32_t*, int, unsigned long long*, int, hipStream_t);
 template hipError_t launch_insert_batch<double>(const RunDesc<double>*, const PArrays<double>&, const Segs&,
@@ -991,13 +1083,30 @@ SPINPIC_INST_PUSH(float, double, 2)
 SPINPIC_INST_PUSH(float, double, 3)
 SPINPIC_INST_PUSH(double, double, 2)
 SPINPIC_INST_PUSH(double, double, 3)
+#define SPINPIC_INST_MARCH(real, acc)                                                           \
+    template hipError_t launch_push_march<real, acc>(const Geom&, const Consts<real>&,          \
+        const PArrays<real>&, const Segs&, const PArrays<real>&, int32_t*, int,                \
+        const Fields<freal>&, int, int, int, hipStream_t);
+SPINPIC_INST_MARCH(float, float)
+SPINPIC_INST_MARCH(float, double)
+SPINPIC_INST_MARCH(double, double)
+SPINPIC_INST_MARCH(float, unsigned long long)
+SPINPIC_INST_MARCH(double, unsigned long long)
+#undef SPINPIC_INST_MARCH
+// deterministic mode: fixed-point current sums
+SPINPIC_INST_PUSH(float, unsigned long long, 2)
+SPINPIC_INST_PUSH(float, unsigned long long, 3)
+SPINPIC_INST_PUSH(double, unsigned long long, 2)
+SPINPIC_INST_PUSH(double, unsigned long long, 3)
 template size_t tile_lds_bytes<float, float>(const Geom&, int);
+template size_t tile_lds_bytes<float, unsigned long long>(const Geom&, int);
+template size_t tile_lds_bytes<double, unsigned long long>(const Geom&, int);
 template size_t tile_lds_bytes<float, double>(const Geom&, int);
 template size_t tile_lds_bytes<double, double>(const Geom&, int);
 
 #define SPINPIC_INST_REST(real, DIM)                                                            \
     template hipError_t launch_push_stash<real, DIM>(const Geom&, const Consts<real>&,         \
-        const PArrays<real>&, const int32_t*, const Fields<freal>&, int, int, hipStream_t);    \
+        const PArrays<real>&, int32_t*, const Fields<freal>&, int, int, hipStream_t);          \
     template hipError_t launch_insert<real, DIM>(const Geom&, const PArrays<real>&,            \
         const Segs&, const PArrays<real>&, const PArrays<real>&, int32_t*, int,                 \
         unsigned long long*, int, hipStream_t);

@@ -23,11 +23,14 @@ PIC_OK, PIC_EINVAL, PIC_ECFL, PIC_EHIP, PIC_ECAPACITY, PIC_ENONFINITE, PIC_ESTAT
 PIC_FP64, PIC_FP32_MIXED = 0, 1
 PIC_ACC_DEFAULT, PIC_ACC_FP32, PIC_ACC_FP64 = 0, 1, 2
 PIC_FLAG_TEST_PARTICLE = 1
+PIC_FLAG_DETERMINISTIC = 2
+PIC_FLAG_CELL_ROWS = 4
 MAX_SPECIES = 4
 PIC_MAX_SPECTRUM_BINS = 1024
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
 EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
             "pic_spectrum", "pic_spectrum_noalloc", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
+            "pic_particles_cells", "pic_test_poison",
             "pic_window", "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
             "pic_batch_init", "pic_batch_step", "pic_batch_polarization", "pic_batch_fields",
             "pic_batch_particles", "pic_batch_info", "pic_batch_tuning", "pic_batch_stats",
@@ -114,6 +117,9 @@ def load_library(path=LIB_PATH):
     D = ctypes.POINTER(ctypes.c_double)
     lib.pic_spectrum.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                  D, D, D]
+    lib.pic_particles_cells.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_test_poison.argtypes = [P, ctypes.c_int32]
     lib.pic_spectrum_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                          D, D, D]
     lib.pic_phase_space.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -199,7 +205,7 @@ def make_config(ndim, n, d, dt, species, precision=PIC_FP64, tile=(0, 0, 0), sla
 
 
 def config_from_spec(spec, precision=None, tile=None, test_particle=False, slack=0.0,
-                     deposit_acc=PIC_ACC_DEFAULT):
+                     deposit_acc=PIC_ACC_DEFAULT, deterministic=False, cell_rows=False):
     """Config from a workload recipe dict (ndim, n, d, dt, species, ...)."""
     if precision is None:
         precision = spec.get("precision", "fp64")
@@ -211,7 +217,9 @@ def config_from_spec(spec, precision=None, tile=None, test_particle=False, slack
             tile = (0, 0, 0)
     return make_config(spec["ndim"], spec["n"], spec["d"], spec["dt"], spec["species"],
                        precision=precision, tile=tile, slack=slack,
-                       flags=PIC_FLAG_TEST_PARTICLE if test_particle else 0,
+                       flags=((PIC_FLAG_TEST_PARTICLE if test_particle else 0) |
+                              (PIC_FLAG_DETERMINISTIC if deterministic else 0) |
+                              (PIC_FLAG_CELL_ROWS if cell_rows else 0)),
                        deposit_acc=deposit_acc)
 
 
@@ -252,8 +260,8 @@ def _make_state(particles, fields, keep):
     for s in range(MAX_SPECIES):
         if s < len(particles) and particles[s] is not None and len(particles[s]):
             arr = np.ascontiguousarray(particles[s], dtype=np.float64)
-            if arr.ndim != 2 or arr.shape[1] != 10:
-                raise ValueError("particles[%d] must have shape (N, 10)" % s)
+            if arr.ndim != 2 or arr.shape[1] not in (10, 13):
+                raise ValueError("particles[%d] must have shape (N, 10), or (N, 13) in cell form" % s)
             keep.append(arr)
             st.count[s] = arr.shape[0]
             st.particles[s] = arr.ctypes.data
@@ -269,7 +277,9 @@ def _make_state(particles, fields, keep):
 
 def pic_init(cfg, particles, fields=None, device=0, memory=None):
     """Create a context.  particles: list of (N, 10) float64 arrays per species
-    (x y z ux uy uz sx sy sz w); fields: (6, nz, ny, nx) float64 or None.
+    (x y z ux uy uz sx sy sz w), or with PIC_FLAG_CELL_ROWS (N, 13) arrays
+    (cx cy cz ox oy oz ux uy uz sx sy sz w); fields: (6, nz, ny, nx) float64
+    or None.
     Returns (ctx, memory) - keep ``memory`` alive as long as the context."""
     lib = load_library()
     keep = []
@@ -307,6 +317,18 @@ def pic_particles(ctx, species, count):
     n = ctypes.c_int64()
     _check(load_library().pic_particles(ctx, int(species), _dptr(out), out.size, ctypes.byref(n)), ctx)
     return out[: n.value]
+
+
+def pic_particles_cells(ctx, species, count):
+    """Rows (id, cx cy cz, ox oy oz, u, s, w) sorted by id, every value exact."""
+    out = np.empty((count, 14))
+    n = ctypes.c_int64()
+    _check(load_library().pic_particles_cells(ctx, int(species), _dptr(out), out.size, ctypes.byref(n)), ctx)
+    return out[: n.value]
+
+
+def pic_test_poison(ctx, species):
+    _check(load_library().pic_test_poison(ctx, int(species)), ctx)
 
 
 def pic_spectrum(ctx, species, emin, emax, nbins):
@@ -429,6 +451,14 @@ class Simulation:
         """Rows (id, x y z, u, s, w) of the particles in the box, sorted by id."""
         count = self.stats()["per_species"][species]
         return pic_particles(self.ctx, species, count)
+
+    def particles_cells(self, species):
+        """Rows (id, cx cy cz, ox oy oz, u, s, w), sorted by id, exact."""
+        count = self.stats()["per_species"][species]
+        return pic_particles_cells(self.ctx, species, count)
+
+    def poison(self, species):
+        pic_test_poison(self.ctx, species)
 
     def window(self, **kw):
         """Open the x faces and start a moving window (see window_config)."""

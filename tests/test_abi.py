@@ -193,3 +193,47 @@ def test_track_calls_validate_without_a_gpu(lib):
     assert lib.pic_track_backward(None, None, None, None, None, None, None) == S.PIC_ESTATE
     assert lib.pic_track_timing(None, None) == S.PIC_ESTATE
     lib.pic_track_free(None)
+
+
+def _cell_row(**cols):
+    p = np.zeros((1, 13))
+    p[0, :] = [3.0, 2.0, 0.0, 0.25, 0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.01]
+    names = ("cx", "cy", "cz", "ox", "oy", "oz", "ux", "uy", "uz", "sx", "sy", "sz", "w")
+    for k, v in cols.items():
+        p[0, names.index(k)] = v
+    return p
+
+
+@pytest.mark.parametrize("cols,needle", [
+    ({"cx": 32.0}, "cell outside"),      # the grid has 32 x 16 cells
+    ({"cy": -1.0}, "cell outside"),
+    ({"cx": 2.5}, "cell outside"),       # not a whole number
+    ({"ox": 1.0}, "offset outside"),
+    ({"oy": -0.1}, "offset outside"),
+    ({"sy": 0.5}, "|s|"),
+    ({"w": math.nan}, "non-finite"),
+])
+def test_T16_init_rejects_bad_cell_rows(lib, cols, needle):
+    """Rows in cell form (PIC_FLAG_CELL_ROWS) are checked before the GPU is touched."""
+    cfg = _good_cfg(flags=S.PIC_FLAG_CELL_ROWS | S.PIC_FLAG_DETERMINISTIC)
+    got, msg, _ = _init_status(lib, cfg, [_cell_row(**cols)])
+    assert got == S.PIC_EINVAL, msg
+    assert needle in msg
+
+
+def test_deterministic_and_cell_rows_not_in_batches(lib):
+    cfg = _good_cfg(flags=S.PIC_FLAG_DETERMINISTIC)
+    st = S.State()
+    for s in range(S.MAX_SPECIES):
+        st.count[s] = 0
+        st.particles[s] = None
+    b = ctypes.c_void_p()
+    assert lib.pic_batch_init(1, ctypes.byref(cfg), ctypes.byref(st), 0, None, None, ctypes.byref(b)) == S.PIC_EINVAL
+    assert "deterministic" in lib.pic_batch_last_error(None).decode()
+
+
+def test_new_hooks_on_null_context(lib):
+    N = ctypes.c_int64()
+    assert lib.pic_particles_cells(None, 0, None, 0, ctypes.byref(N)) == S.PIC_ESTATE
+    assert lib.pic_test_poison(None, 0) == S.PIC_ESTATE
+    assert lib.pic_spectrum_noalloc(None, 0, 0.0, 1.0, 4, None, None, None) == S.PIC_ESTATE

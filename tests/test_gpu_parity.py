@@ -431,3 +431,50 @@ def test_fp32_test_particle_bound_1e5(design):
         _say("species", k, "max position %.2e momentum %.2e spin %.2e" % (pos.max(), mom.max(), spin.max()))
         assert pos.max() <= 1e-5 and mom.max() <= 1e-5 and spin.max() <= 1e-5
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_nonfinite_probe_T16(precision):
+    """A NaN planted in one particle's momentum (the test hook) is caught by
+    the push kernels' probe: after the next step pic_polarization and
+    pic_energy return PIC_ENONFINITE, and pic_step returns it at its next
+    check (it reads the probe every 16 steps)."""
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    _say("non-finite probe", precision)
+    sim = S.Simulation(S.config_from_spec(spec, precision=precision), state["particles"], state["fields"])
+    sim.step(3)
+    sim.polarization()
+    sim.energy()
+    sim.poison(0)
+    sim.step(1)
+    for call in (sim.polarization, sim.energy):
+        with pytest.raises(S.PicError) as ei:
+            call()
+        assert ei.value.code == S.PIC_ENONFINITE
+    with pytest.raises(S.PicError) as ei:
+        for _ in range(20):
+            sim.step(1)
+    assert ei.value.code == S.PIC_ENONFINITE
+    assert sim.stats()["steps"] <= 17
+    sim.close()
+
+
+@pytest.mark.parametrize("run,xcd", [(1, 0), (2, 0), (2, 1), (8, 1)])
+def test_3d_marching_push_runs(run, xcd, monkeypatch):
+    """The 3D push marches along z over runs of tiles, carrying the shared
+    field and current planes between the tiles of a run.  Runs of one tile
+    (the single-tile kernel), of two (a run boundary inside every column of
+    three tiles, the last one ragged: 10 cells of 4), of eight (whole
+    columns), in launch order and in per-XCD ranges: all match the oracle."""
+    monkeypatch.setenv("SPINPIC_PUSH_RUN", str(run))
+    monkeypatch.setenv("SPINPIC_PUSH_XCD", str(xcd))
+    spec = synth.preset("small3d")
+    _say("3d marching push, run", run, "xcd ranges", xcd)
+    sim, ref = _pair(spec, tile=(4, 4, 4))
+    for n in (5, 10):
+        sim.step(5)
+        ref.step(5)
+        _compare(sim, ref, spec, 1e-9, 1e-9, label="run %d step %d" % (run, n))
+    assert sim.energy()[-1] < 1e-11
+    sim.close()
