@@ -368,6 +368,10 @@ def bench_tracking(args):
     flops = n * ns * (TRACK_FLOP_FORWARD + TRACK_FLOP_BACKWARD)
     peak = FP32_VECTOR_PEAK_TFLOPS if precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
     achieved = flops / ((f_ms + b_ms) * 1e-3) / 1e12
+    # the backward pass writes each recomputed state (9 values) to its
+    # segment's scratch and reads it back once, and reads the kept states
+    r = 4 if precision == "fp32" else 8
+    bwd_bytes = n * ns * 9 * r * 2 + n * (ns // spec["checkpoint"]) * 9 * r
     result = {
         "metric": "differentiable spin-tracking particle-steps/sec (forward + adjoint)",
         "value": n * ns / ((f_ms + b_ms) * 1e-3), "unit": "particle-steps/s", "n_gpus": 1,
@@ -381,7 +385,10 @@ def bench_tracking(args):
                      "frac": achieved / peak, "traffic": None,
                      "kernel": "k_track_forward + k_track_backward",
                      "flop_per_particle_step": TRACK_FLOP_FORWARD + TRACK_FLOP_BACKWARD,
-                     "forward_ms": f_ms, "backward_ms": b_ms},
+                     "forward_ms": f_ms, "backward_ms": b_ms,
+                     "backward_hbm": {"bytes_per_call": bwd_bytes,
+                                      "achieved_GBps": bwd_bytes / (b_ms * 1e-3) / 1e9,
+                                      "frac": bwd_bytes / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}},
         "result": {"P": list(P), "dJ_dE0": gth[0], "dJ_dkp": gth[1]},
     }
     if not args.no_cpu_baseline:
@@ -690,9 +697,14 @@ def compare_runs(spec, r32, r64):
             e = particle_errors(r32["sample"][k], r64["sample"][k], spec, k)
             per[sp.get("name", str(k))] = {
                 "particles": int(e.size), "median": float(np.median(e)),
-                "q99": float(np.percentile(e, 99)), "max": float(e.max())}
+                "q99": float(np.percentile(e, 99)), "max": float(e.max()),
+                "fraction_above_1e-5": float(np.mean(e > 1e-5))}
+        # the workload's per-particle bound: met by the push on its own in
+        # test-particle mode; in the laser-driven plasma the fastest electrons
+        # amplify the rounding of their float32 state beyond it
         res["per_particle_fp32_vs_fp64"] = dict(per, after_steps=r32["sample_step"],
-                                                sampled="every 64th particle by id")
+                                                sampled="every 64th particle by id", bound=1e-5,
+                                                bound_met=all(v["max"] <= 1e-5 for v in per.values()))
     return res
 
 
@@ -852,7 +864,8 @@ def main():
         result["fp64_compare"] = dict({
             "value": npart * args.steps / r64["elapsed"], "unit": "pushes/s",
             "ms_per_step": r64["elapsed"] / args.steps * 1e3,
-            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS},
+            "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r64["timers"].items()}},
             **compare_runs(spec, r, r64))
         if full:
             result["fp64_compare"]["full_run"] = full_run_summary(r64, npart)
@@ -942,6 +955,7 @@ def bench_other(S, workload, args, compare):
             "value": npart * args.steps / r64["elapsed"], "unit": "pushes/s",
             "ms_per_step": r64["elapsed"] / args.steps * 1e3,
             "push_avg_launch_ms": t64 * 1e3, "push_hbm_frac": lb64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in r64["timers"].items()},
             "full_run": full_run_summary(r64, npart)}, **compare_runs(spec, r, r64))
     return out
 

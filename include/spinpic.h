@@ -111,7 +111,8 @@ typedef struct {
     int32_t tile[3];     /* tile edge in cells per axis; 0 selects the default
                             (16x16 in 2D, 12x6x6 in 3D FP32, 6x6x6 in 3D FP64) */
     double slack;        /* spare capacity per tile segment as a fraction of its
-                            initial population (>= 0; 0 selects 0.25) */
+                            initial population (>= 0; 0 selects 0.25, or 1.0 for
+                            3D FP64 with its smaller default tiles) */
     int32_t flags;       /* PIC_FLAG_* */
     int32_t deposit_acc; /* PIC_FP32_MIXED only: precision of the per-tile
                             shared-memory current sums that precede the one FP64
@@ -141,7 +142,9 @@ typedef struct pic_ctx pic_ctx;
 
 /* Validate cfg, copy the initial state to the device sorted by tile, and
  * return a new context in *out.  Errors: PIC_EINVAL (bad sizes, species,
- * tile, precision, non-unit spin, non-finite input), PIC_ECFL, PIC_ENOMEM,
+ * tile, precision, non-unit spin (| |s|^2 - 1 | above 1e-6, or 1e-4 with
+ * PIC_FP32_MIXED, whose spins drift by that much over thousands of steps),
+ * non-finite input, cell rows out of range), PIC_ECFL, PIC_ENOMEM,
  * PIC_EHIP.  alloc may be NULL; hip_stream may be NULL (the null stream). */
 int pic_init(const pic_config* cfg, const pic_state* init, const pic_allocator* alloc,
              void* hip_stream, pic_ctx** out);

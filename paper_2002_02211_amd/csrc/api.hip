@@ -140,7 +140,12 @@ Status resolve_config(const pic_config* cfg, const pic_state* init, Resolved& R)
     // on gfx950 (measured on the c2 workload)
     R.use_acc64 = c.precision == PIC_FP64 || c.deposit_acc != PIC_ACC_FP32;
     if (c.slack < 0.0 || !std::isfinite(c.slack)) return fail(PIC_EINVAL, "slack must be >= 0");
-    R.slack = c.slack > 0.0 ? c.slack : 0.25;
+    // default slack: 25 %; 100 % for 3D FP64, whose 6 x 6 x 6 tiles hold half
+    // as many particles per segment as the FP32 ones, so that compression by
+    // a laser fills them sooner (c3 FP64 with 25 %: steps 10-60 took 112 ms
+    // each with the push at 10.5 ms, the overflow store's push from global
+    // memory taking the rest)
+    R.slack = c.slack > 0.0 ? c.slack : (c.ndim == 3 && c.precision == PIC_FP64 ? 1.0 : 0.25);
     for (int a = 0; a < 3; ++a) {
         if (a >= c.ndim) {
             R.T[a] = 1;
@@ -470,6 +475,14 @@ static long long seg_capacity(long long count, double slack) {
     return round_up((long long)std::ceil(count * (1.0 + slack)) + 32, 32);
 }
 
+// Tiles per z-run of the 3D marching push; 1 runs the single-tile push.
+// Measured on c3 (12 x 6 x 6 tiles, counters over 24 launches): runs of 8
+// tiles fetch 13.8 GB per launch instead of 15.5 (per-XCD ranges of runs:
+// 10.1 GB) yet take 5.24 ms instead of 5.05 (5.95 ms): the 3D push is held
+// by its instruction stream and shared-memory conflicts, not by its HBM
+// traffic, so the single-tile push stays the default.
+constexpr int kMarchRun = 1;
+
 // Overflow policy.  Every kStashCheck steps the step loop waits for its
 // stream, so that the pinned copy of the overflow count is current (the host
 // can otherwise run many steps ahead of the GPU), and folds the overflow
@@ -477,9 +490,6 @@ static long long seg_capacity(long long count, double slack) {
 // particles, or any at all on a kStashPeriod boundary: overflow particles are
 // pushed from global memory at a fraction of the tile push's rate.
 constexpr int kStashCheck = 16;
-
-// Tiles per z-run of the 3D marching push.
-constexpr int kMarchRun = 8;
 constexpr int kStashPeriod = 64;
 constexpr long long kStashFrac = 512;
 constexpr int kStashBlocks = 1024;
@@ -533,9 +543,9 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     deposit_ = (c.flags & PIC_FLAG_TEST_PARTICLE) ? 0 : 1;
     use_acc64_ = R.use_acc64;
     det_ = R.det;
-    // 3D: the push marches along z over runs of kMarchRun tiles (overridable
-    // by SPINPIC_PUSH_RUN, 1 = one tile per workgroup, for measurements);
-    // it needs tiles of at least 3 cells along z
+    // 3D: the push may march along z over runs of tiles (kMarchRun, or
+    // SPINPIC_PUSH_RUN for measurements; 1 = one tile per workgroup); it
+    // needs tiles of at least 3 cells along z
     march_R_ = 1;
     if (DIM == 3 && g_.T[2] >= 3) {
         march_R_ = kMarchRun;
@@ -624,6 +634,10 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     // different shared-memory words instead of serializing on one.
     const int tile_cells = g_.T[0] * g_.T[1] * g_.T[2];
     double zw_sum = 0.0;   // sum of |Z w|: no node's current can exceed it
+    // |s|^2 must be 1: to 1e-6 in FP64; in FP32 to 1e-4, since float32 spins
+    // rotated over thousands of steps (a restart's input) drift by more than
+    // 1e-6 from unit length
+    const double s2_tol = std::is_same<real, float>::value ? 1e-4 : 1e-6;
     std::vector<int32_t> segof((size_t)npart_);
     std::vector<uint32_t> key((size_t)npart_);
     {
@@ -639,7 +653,7 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
                         return fail(PIC_EINVAL, "species %d particle %lld: non-finite input", s, i);
                 const double* sv = row + cu + 3;
                 const double s2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
-                if (std::fabs(s2 - 1.0) > 1e-6)
+                if (std::fabs(s2 - 1.0) > s2_tol)
                     return fail(PIC_EINVAL, "species %d particle %lld: |s| = %.9f, must be 1", s, i,
                                 std::sqrt(s2));
                 zw_sum += Zs * std::fabs((double)(real)row[cu + 6]);
