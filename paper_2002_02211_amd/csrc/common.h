@@ -391,44 +391,36 @@ __device__ inline real displacement(real v, const Consts<real>& k, int a) {
 // Advance one offset by disp cells (|disp| < 1); returns the cell change
 // (-1, 0, +1) and leaves the new offset in [0, 1).  If an offset just below
 // a cell edge rounds up to 1, the particle is placed at the edge of the
-// next cell instead.
+// next cell instead.  Written with selects, not branches: the lanes of a
+// wavefront take different cases, and branches made every lane walk all
+// of them with exec-mask juggling around each.
 template <typename real>
 __device__ inline int advance_offset(real& o, real disp) {
-    real x = o + disp;
-    int dc = 0;
-    if (x >= real(1)) {
-        x -= real(1);
-        dc = 1;
-    } else if (x < real(0)) {
-        x += real(1);
-        dc = -1;
-        if (x >= real(1)) {
-            x = real(0);
-            dc = 0;
-        }
-    }
-    o = x;
-    return dc;
+    const real x = o + disp;
+    const bool up = x >= real(1);
+    const bool dn = x < real(0);
+    const real y = up ? x - real(1) : (dn ? x + real(1) : x);
+    const int dc = up ? 1 : (dn ? -1 : 0);
+    // x in (-ulp, 0) wraps to x + 1, which can round to 1
+    const bool tie = dn && y >= real(1);
+    o = tie ? real(0) : y;
+    return tie ? 0 : dc;
 }
 
 // CIC shape factors before and after the move on the three nodes b, b+1, b+2
 // with b = min(old cell, new cell).  Returns b relative to the old cell
-// (0 or -1).
+// (0 or -1).  Selects, as above.
 template <typename real>
 __device__ inline int shape_pair(real o0, real o1, int dc, real S0[3], real S1[3]) {
-    if (dc == 0) {
-        S0[0] = real(1) - o0; S0[1] = o0; S0[2] = real(0);
-        S1[0] = real(1) - o1; S1[1] = o1; S1[2] = real(0);
-        return 0;
-    }
-    if (dc > 0) {
-        S0[0] = real(1) - o0; S0[1] = o0; S0[2] = real(0);
-        S1[0] = real(0); S1[1] = real(1) - o1; S1[2] = o1;
-        return 0;
-    }
-    S0[0] = real(0); S0[1] = real(1) - o0; S0[2] = o0;
-    S1[0] = real(1) - o1; S1[1] = o1; S1[2] = real(0);
-    return -1;
+    const bool neg = dc < 0, pos = dc > 0;
+    const real a0 = real(1) - o0, a1 = real(1) - o1;
+    S0[0] = neg ? real(0) : a0;
+    S0[1] = neg ? a0 : o0;
+    S0[2] = neg ? o0 : real(0);
+    S1[0] = pos ? real(0) : a1;
+    S1[1] = pos ? a1 : o1;
+    S1[2] = pos ? o1 : real(0);
+    return neg ? -1 : 0;
 }
 
 // Esirkepov current of one particle.  sink(c, i, j, k, v) adds v to J_c at
