@@ -2049,23 +2049,39 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     for (int b = 0; b < 2; ++b)
         for (int a = 0; a < 3; ++a) HIP_OR_FAIL(hipMemsetAsync(jbuf_[b][a], 0, ncells_ * sizeof(freal), stream_));
 
-    // ---- work list: each run's tiles in row-major order, cut into 8
-    // contiguous chunks of about equal cost (particles + cells), one per XCD
+    // ---- work list: each run's tiles in row-major order (neighbouring
+    // tiles side by side, their guard cells shared in L2), the runs by
+    // decreasing cost per tile, cut into 8 contiguous chunks of about equal
+    // cost (particles + cells), one per XCD.  The persistent push takes the
+    // chunks front to back, so the tiles left at the end, when workgroups
+    // run out of work one by one, are the cheapest ones.
     order_.resize(ntiles_);
     {
+        auto tile_cost = [&](const Run& R, int t) {
+            long long c = 0;
+            for (int s = 0; s < nsp_; ++s) c += count[R.sid_base + t * nsp_ + s];
+            const int tx = t % R.g.nt[0], ty = t / R.g.nt[0];
+            const long long cells = (long long)std::min(R.g.T[0], R.g.n[0] - tx * R.g.T[0]) *
+                                    std::min(R.g.T[1], R.g.n[1] - ty * R.g.T[1]);
+            return (double)(c + cells);
+        };
+        std::vector<double> run_cost(nrun, 0.0);
+        std::vector<int> rorder(nrun);
+        for (int r = 0; r < nrun; ++r) {
+            rorder[r] = r;
+            for (int t = 0; t < runs_[r].g.ntiles; ++t) run_cost[r] += tile_cost(runs_[r], t);
+            run_cost[r] /= std::max(runs_[r].g.ntiles, 1);
+        }
+        std::stable_sort(rorder.begin(), rorder.end(), [&](int a, int b) { return run_cost[a] > run_cost[b]; });
         std::vector<double> cost(ntiles_);
         double total = 0.0;
-        for (int r = 0; r < nrun; ++r) {
+        int i = 0;
+        for (int r : rorder) {
             const Run& R = runs_[r];
-            for (int t = 0; t < R.g.ntiles; ++t) {
-                long long c = 0;
-                for (int s = 0; s < nsp_; ++s) c += count[R.sid_base + t * nsp_ + s];
-                const int tx = t % R.g.nt[0], ty = t / R.g.nt[0];
-                const long long cells = (long long)std::min(R.g.T[0], R.g.n[0] - tx * R.g.T[0]) *
-                                        std::min(R.g.T[1], R.g.n[1] - ty * R.g.T[1]);
-                order_[R.tile_base + t] = TileRef{r, t};
-                cost[R.tile_base + t] = (double)(c + cells);
-                total += (double)(c + cells);
+            for (int t = 0; t < R.g.ntiles; ++t, ++i) {
+                order_[i] = TileRef{r, t};
+                cost[i] = tile_cost(R, t);
+                total += cost[i];
             }
         }
         xq_.start[0] = 0;
