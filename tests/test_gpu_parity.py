@@ -388,15 +388,20 @@ def test_fp32_cell_edge_ties(test_particle):
 
 
 STATIC_FIELD_DESIGNS = {
-    # name: (uniform amplitude, smooth amplitude, kmax); a pair is (for E, for B)
-    "runaway": (3.0, 0.3, 1),                       # E and B at the c1 laser's a0 = 3: electrons reach |u| ~ 30
-    "accelerating": (0.3, 0.03, 2),                 # E and B at a tenth of it: |u| ~ 6
-    "magnetized": ((0.3, 3.0), (0.03, 0.3), 2),     # B at a0 = 3, E at a tenth: gyration, drifts
+    # name: (uniform amplitude, smooth amplitude, kmax, seed); a pair is (for E, for B)
+    "runaway": (3.0, 0.3, 1, 3),                    # E and B at the c1 laser's a0 = 3: electrons reach |u| ~ 30
+    "accelerating": (0.3, 0.03, 2, 3),              # E and B at a tenth of it: |u| ~ 6
+    "magnetized": ((0.3, 3.0), (0.03, 0.3), 2, 3),  # B at a0 = 3, E at a tenth: gyration, drifts
+    "magnetized_k1": ((0.3, 3.0), (0.03, 0.3), 1, 3),
+    "magnetized_seed5": ((0.3, 3.0), (0.03, 0.3), 1, 5),
+    "magnetized_k2_seed5": ((0.3, 3.0), (0.03, 0.3), 2, 5),
+    "magnetized_steep": ((0.3, 3.0), (0.1, 1.0), 1, 3),  # three times the field variation
 }
-# Not gated: B at a0 = 3 with a 10 % gradient of E and B across the box.
-# There the FP32 rotation's roundings, amplified by the gradient drift, take
-# the worst electron to 1.0e-5 in position and 1.3e-5 in momentum (float32
-# storage alone: 4.3e-6 and 2.4e-6).
+# Not gated: B at a0 = 3 with E's smooth part as large as its uniform part
+# ((0.3, 3.0), 0.3, 1, seed 3).  There the worst electron reaches 1.0e-5 in
+# position and 1.3e-5 in momentum (float32 storage alone: 4.3e-6 and
+# 2.4e-6); in that design it moves by a factor of two with any change of
+# rounding, FP64 arithmetic in the step included.
 
 
 @pytest.mark.parametrize("design", sorted(STATIC_FIELD_DESIGNS))
@@ -414,11 +419,11 @@ def test_fp32_test_particle_bound_1e5(design):
     momenta and spins and the static fields rounded to float32 once, so the
     comparison measures 100 steps of FP32 arithmetic and storage, not the
     rounding of the inputs."""
-    U, V, K = STATIC_FIELD_DESIGNS[design]
+    U, V, K, seed = STATIC_FIELD_DESIGNS[design]
     spec = synth.preset("c1")
     state0 = synth.make_state(spec)
     parts = [p[::4].copy() for p in state0["particles"]]
-    fields = synth.make_static_fields(spec, U, V, kmax=K, seed=3).astype(np.float32).astype(np.float64)
+    fields = synth.make_static_fields(spec, U, V, kmax=K, seed=seed).astype(np.float32).astype(np.float64)
     state = fp32_rounded_state(spec, {"particles": parts, "fields": fields})
     _say("fp32 test-particle 1e-5 bound,", design, "fields, c1 particles / 4, 100 steps")
     sim = S.Simulation(S.config_from_spec(spec, precision="fp32", test_particle=True),
