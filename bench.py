@@ -159,7 +159,8 @@ def write_traffic(fetch_csv, write_csv, workload, precision, probe_mib=1024):
     cf_mean, cf_n = fetch[copy[0]]
     f_fetch = probe / (cf_mean * cf_n)
     f_write = probe / write[fill[0]][0]
-    push = [k for k in fetch if "k_push_tiles" in k]
+    # the push without the per-step Eq. 4 record (the bench also runs the one with it)
+    push = [k for k in fetch if "k_push_tiles" in k and "true>" not in k]
     if len(push) != 1:
         raise SystemExit("expected one push kernel instantiation, found %s" % push)
     pf, n_f = fetch[push[0]]
@@ -680,6 +681,36 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
     return out
 
 
+def time_record(sim, steps=20):
+    """What the per-step Eq. 4 record costs: the push over `steps` steps
+    without and then with the record of the whole ensemble (events around the
+    push), against one on-demand pic_polarization call (wall clock, including
+    its wait and copy); and whether the record's last step equals the
+    on-demand result of the same state."""
+    import numpy as np
+    import torch
+    sim.timing(True, push_only=True)
+    sim.step(steps)
+    a = sim.timing_read()["push_deposit"]
+    sim.timing(False)
+    sim.record_polarization(-1, capacity=steps)
+    sim.timing(True, push_only=True)
+    sim.step(steps)
+    b = sim.timing_read()["push_deposit"]
+    sim.timing(False)
+    P, N = sim.polarization_history()
+    sim.record_polarization(-1, capacity=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Pn, Nn = sim.polarization()
+    t_call = time.perf_counter() - t0
+    push, push_rec = a[0] / max(a[1], 1), b[0] / max(b[1], 1)
+    return {"steps": steps, "at_step": sim.stats()["steps"], "push_ms": push, "push_ms_with_record": push_rec,
+            "record_overhead": push_rec / push - 1.0, "pic_polarization_call_ms": t_call * 1e3,
+            "last_step_equals_on_demand": bool(len(N) == steps and N[-1] == Nn
+                                               and np.allclose(P[-1], Pn, rtol=0.0, atol=1e-12))}
+
+
 def compare_runs(spec, r32, r64):
     """FP32-mixed against FP64 on the same workload and step schedule."""
     import numpy as np
@@ -815,9 +846,13 @@ def main():
     acc = {"default": S.PIC_ACC_DEFAULT, "fp32": S.PIC_ACC_FP32, "fp64": S.PIC_ACC_FP64}[args.deposit_acc]
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     full = None if (args.window or args.no_full_run) else spec["steps"]
-    diag = (lambda sim: time_diagnostics(sim, spec, npart, precision)) if args.diagnostics else None
+    def at_end(sim):
+        extra = {"record": time_record(sim)}
+        if args.diagnostics:
+            extra["diagnostics"] = time_diagnostics(sim, spec, npart, precision)
+        return extra
     r = run_schedule(S, spec, state, precision, acc, args.warmup, args.steps, tile, window=args.window,
-                     slack=args.slack, full_steps=full, on_open=diag)
+                     slack=args.slack, full_steps=full, on_open=at_end)
     stats = r["stats_timed"]
     if args.window:
         npart = stats["particles"]   # injected minus removed since the start
@@ -853,8 +888,9 @@ def main():
     }
     if full:
         result["full_run"] = full_run_summary(r, npart)
-    if "extra" in r:
-        result["diagnostics"] = r["extra"]
+    result["polarization_record"] = r["extra"]["record"]
+    if "diagnostics" in r["extra"]:
+        result["diagnostics"] = r["extra"]["diagnostics"]
 
     if precision == "fp32" and not args.no_fp64_compare:
         r64 = run_schedule(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps, tile,

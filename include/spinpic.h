@@ -164,6 +164,34 @@ int pic_step(pic_ctx* ctx, int32_t nsteps);
 int pic_polarization(pic_ctx* ctx, int32_t species, double ekin_min_mev,
                      double ekin_max_mev, double P_out[3], int64_t* N_out);
 
+#define PIC_MAX_RECORD_STEPS 65536
+
+/* Per-step record of section 2 Eq. 4, summed by the push kernels while they
+ * push (no pass over the particles of its own).  From this call on, every
+ * step of pic_step records the mean spin and the count of the particles the
+ * selection takes (species, or -1 for all; kinetic energy in
+ * [ekin_min_mev, ekin_max_mev) MeV as for pic_polarization, infinite bounds
+ * allowed) in the state the step leaves: what pic_polarization would return
+ * after that step.  It differs from that only by the order of the FP64 sums,
+ * and, with a moving window, the particles injected at the end of a step
+ * enter from the next step on.  capacity (1 .. PIC_MAX_RECORD_STEPS): steps
+ * the record holds; pic_step returns PIC_ECAPACITY, before enqueuing a step
+ * that would not fit, until pic_polarization_history has emptied it.
+ * capacity 0 stops recording and frees the record; another call starts a
+ * new, empty one (after waiting for the stream).  Device memory: capacity x
+ * 1 KiB, through the allocator.  Not in the deterministic mode (PIC_EINVAL). */
+int pic_polarization_record(pic_ctx* ctx, int32_t species, double ekin_min_mev,
+                            double ekin_max_mev, int32_t capacity);
+
+/* The steps recorded since the record started or was last read, oldest
+ * first: P_out[3 k .. 3 k + 2] the mean spin and N_out[k] the count of the
+ * k-th (P 0 where the count is 0); *nsteps_out of them, 0 when no record is
+ * kept.  cap: the entries N_out has room for (P_out: 3 cap); less than the
+ * steps recorded is PIC_EINVAL.  Waits for the stream, then empties the
+ * record.  PIC_ENONFINITE as pic_polarization. */
+int pic_polarization_history(pic_ctx* ctx, double* P_out, int64_t* N_out, int32_t cap,
+                             int32_t* nsteps_out);
+
 /* Copy the masked components (PIC_EX ... PIC_RHO, in bit order) to host_out
  * as float64, each [nz][ny][nx] with x fastest.  J is the current of the last
  * step.  cap_doubles must hold popcount(mask)*cells values.  Waits. */

@@ -267,6 +267,8 @@ public:
     virtual Status init(const Resolved& R, const pic_state* st) = 0;
     virtual Status step(int n) = 0;
     virtual Status polarization(int species, double emin, double emax, double P[3], int64_t* N) = 0;
+    virtual Status record(int species, double emin, double emax, int capacity) = 0;
+    virtual Status record_read(double* P, int64_t* N, int cap, int* n_out) = 0;
     virtual Status fields(uint32_t mask, double* out, size_t cap) = 0;
     virtual Status particles(int species, double* out, size_t cap, int64_t* n, bool cells = false) = 0;
     virtual Status poison(int species) = 0;
@@ -299,6 +301,8 @@ public:
     Status init(const Resolved& R, const pic_state* st) override;
     Status step(int n) override;
     Status polarization(int species, double emin, double emax, double P[3], int64_t* N) override;
+    Status record(int species, double emin, double emax, int capacity) override;
+    Status record_read(double* P, int64_t* N, int cap, int* n_out) override;
     Status fields(uint32_t mask, double* out, size_t cap) override;
     Status particles(int species, double* out, size_t cap, int64_t* n, bool cells = false) override;
     Status poison(int species) override;
@@ -416,6 +420,12 @@ private:
     freal* scratch_ = nullptr;     // one field array, for the shifts
     Segs seg_tmp_{};               // a second segment table, for the shifts
     long long npart_bound_ = 0;    // stored entries at the last count + injected since
+    // per-step Eq. 4 record (pic_polarization_record)
+    bool rec_on_ = false;
+    RecArgs rec_{};                // selection; acc set per step
+    double* rec_buf_ = nullptr;    // rec_cap_ steps x kRecSlots x kRecStride sums
+    int rec_cap_ = 0;
+    int rec_n_ = 0;                // steps recorded since the last read
     Timer timer_;
 };
 
@@ -851,6 +861,9 @@ void Engine<real, DIM>::tstop(int k) {
 template <typename real, int DIM>
 Status Engine<real, DIM>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
+        if (rec_on_ && rec_n_ >= rec_cap_)
+            return fail(PIC_ECAPACITY, "the polarization record is full (%d steps): read it with "
+                        "pic_polarization_history", rec_cap_);
         if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
             HIP_OR_FAIL(hipStreamSynchronize(stream_));
             if (h_ctr_[CTR_NONFINITE])
@@ -862,12 +875,15 @@ Status Engine<real, DIM>::step(int nsteps) {
             }
         }
         const int slot = (int)(nstep_ & 1);
+        // the step's slot of the Eq. 4 record, if one is kept
+        RecArgs rec = rec_;
+        rec.acc = rec_on_ ? rec_buf_ + (size_t)rec_n_ * kRecSlots * kRecStride : nullptr;
         // this step deposits into the zeroed buffer; the field update zeroes
         // the previous step's buffer behind it
         const int jnext = jcur_ ^ 1;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jnext][a];
         tstart(0);
-        if (march_R_ > 1) {
+        if (march_R_ > 1 && !rec_on_) {
             if (det_)
                 HIP_OR_FAIL((launch_push_march<real, unsigned long long>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_,
                                                                          march_R_, march_xcd_, stream_)));
@@ -879,15 +895,17 @@ Status Engine<real, DIM>::step(int nsteps) {
                                                            march_xcd_, stream_)));
         } else if (det_) {
             HIP_OR_FAIL((launch_push_tiles<real, unsigned long long, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_,
-                                                                          stream_)));
+                                                                          rec, stream_)));
         } else if (use_acc64_) {
-            HIP_OR_FAIL((launch_push_tiles<real, double, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
+            HIP_OR_FAIL((launch_push_tiles<real, double, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, rec,
+                                                              stream_)));
         } else {
-            HIP_OR_FAIL((launch_push_tiles<real, real, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, stream_)));
+            HIP_OR_FAIL((launch_push_tiles<real, real, DIM>(g_, k_, p_, seg_, lv_, ctr_, slot, f_, deposit_, rec,
+                                                            stream_)));
         }
         tstop(0);
         tstart(1);
-        HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, kStashBlocks, stream_)));
+        HIP_OR_FAIL((launch_push_stash<real, DIM>(g_, k_, st_, ctr_, f_, deposit_, rec, kStashBlocks, stream_)));
         // the deterministic mode's fixed-point current becomes FP64 for the field update
         if (det_ && deposit_) HIP_OR_FAIL(launch_fixed_to_double(f_.J, g_.ncells, fx_inv_, stream_));
         tstop(1);
@@ -920,6 +938,7 @@ Status Engine<real, DIM>::step(int nsteps) {
         if (deposit_) jcur_ = jnext;
         for (int a = 0; a < 3; ++a) f_.J[a] = jbuf_[jcur_][a];
         ++nstep_;
+        if (rec_on_) ++rec_n_;
         if (win_on_) {
             // the window has moved (n - n0) speed dt; shift once per whole
             // shift_cells cells of that (evaluated as written, in FP64)
@@ -1076,6 +1095,66 @@ Status Engine<real, DIM>::polarization(int species, double emin, double emax, do
     }
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(P[a])) return fail(PIC_ENONFINITE, "polarization is not finite");
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::record(int species, double emin, double emax, int capacity) {
+    if (species < -1 || species >= g_.nsp) return fail(PIC_EINVAL, "species %d out of range", species);
+    if (std::isnan(emin) || std::isnan(emax)) return fail(PIC_EINVAL, "energy window is NaN");
+    if (capacity < 0 || capacity > PIC_MAX_RECORD_STEPS)
+        return fail(PIC_EINVAL, "capacity %d outside 0..%d", capacity, PIC_MAX_RECORD_STEPS);
+    if (det_ && capacity > 0) return fail(PIC_EINVAL, "no per-step polarization record in the deterministic mode");
+    // steps already enqueued may still add into the old record
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    dfree(rec_buf_);
+    rec_buf_ = nullptr;
+    rec_on_ = false;
+    rec_cap_ = rec_n_ = 0;
+    if (capacity == 0) return Status{};
+    const long long nval = (long long)capacity * kRecSlots * kRecStride;
+    rec_buf_ = (double*)dalloc((size_t)nval * sizeof(double));
+    if (!rec_buf_) return fail(PIC_ENOMEM, "polarization record of %d steps: out of device memory", capacity);
+    HIP_OR_FAIL(launch_fill_zero(rec_buf_, nval, stream_));
+    rec_ = RecArgs{};
+    rec_.species = species;
+    rec_.window = !(emin == -HUGE_VAL && emax == HUGE_VAL);
+    rec_.emin = emin;
+    rec_.emax = emax;
+    for (int s = 0; s < kMaxSpecies; ++s) rec_.mu[s] = s < g_.nsp ? R_.cfg.sp[s].mu : 1.0;
+    rec_cap_ = capacity;
+    rec_on_ = true;
+    return Status{};
+}
+
+template <typename real, int DIM>
+Status Engine<real, DIM>::record_read(double* P, int64_t* N, int cap, int* n_out) {
+    *n_out = 0;
+    if (!rec_on_ || rec_n_ == 0) return Status{};
+    if (!P || !N) return fail(PIC_EINVAL, "output arrays must not be NULL");
+    if (cap < rec_n_) return fail(PIC_EINVAL, "cap %d is less than the %d steps recorded", cap, rec_n_);
+    bool bad = false;
+    Status S = nonfinite_flag(&bad);
+    if (S.code) return S;
+    if (bad) return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin");
+    const long long nval = (long long)rec_n_ * kRecSlots * kRecStride;
+    std::vector<double> h((size_t)nval);
+    HIP_OR_FAIL(hipMemcpyAsync(h.data(), rec_buf_, nval * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    for (int k = 0; k < rec_n_; ++k) {
+        double sum[kRecStride] = {0.0, 0.0, 0.0, 0.0};
+        for (int sl = 0; sl < kRecSlots; ++sl)
+            for (int q = 0; q < kRecStride; ++q) sum[q] += h[((size_t)k * kRecSlots + sl) * kRecStride + q];
+        const double n = sum[3];
+        N[k] = (int64_t)std::llround(n);
+        for (int a = 0; a < 3; ++a) {
+            P[3 * k + a] = n > 0 ? sum[a] / n : 0.0;
+            if (!std::isfinite(P[3 * k + a])) return fail(PIC_ENONFINITE, "recorded polarization is not finite");
+        }
+    }
+    HIP_OR_FAIL(launch_fill_zero(rec_buf_, nval, stream_));
+    *n_out = rec_n_;
+    rec_n_ = 0;
     return Status{};
 }
 
@@ -2479,6 +2558,24 @@ int pic_polarization(pic_ctx* ctx, int32_t species, double emin, double emax, do
         return PIC_EINVAL;
     }
     return finish(ctx, ctx->eng->polarization(species, emin, emax, P_out, N_out));
+}
+
+int pic_polarization_record(pic_ctx* ctx, int32_t species, double ekin_min_mev, double ekin_max_mev,
+                            int32_t capacity) {
+    CTX_CHECK(ctx);
+    return finish(ctx, ctx->eng->record(species, ekin_min_mev, ekin_max_mev, capacity));
+}
+
+int pic_polarization_history(pic_ctx* ctx, double* P_out, int64_t* N_out, int32_t cap, int32_t* nsteps_out) {
+    CTX_CHECK(ctx);
+    if (!nsteps_out) {
+        ctx->err = "nsteps_out must not be NULL";
+        return PIC_EINVAL;
+    }
+    int n = 0;
+    const int code = finish(ctx, ctx->eng->record_read(P_out, N_out, cap, &n));
+    *nsteps_out = n;
+    return code;
 }
 
 int pic_fields(pic_ctx* ctx, uint32_t mask, double* host_out, size_t cap_doubles) {

@@ -17,6 +17,7 @@
 namespace spinpic {
 
 constexpr int kMaxSpecies = 4;
+constexpr double kMeC2MeV = 0.51099895;   // electron rest energy, MeV
 constexpr int kBlock = 256;   // threads per workgroup: 4 wave64
 
 // ---------------------------------------------------------------- layout

@@ -458,7 +458,6 @@ __device__ inline void block_sum_add(double (&v)[NV], double* acc) {
     }
 }
 
-constexpr double kMeC2MeV = 0.51099895;   // electron rest energy
 
 template <typename real, int DIM>
 __device__ inline void reduce_one(int mode, const PArrays<real>& p, long long i, int sp,

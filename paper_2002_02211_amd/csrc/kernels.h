@@ -10,10 +10,26 @@ using freal = double;   // grid fields E, B, J
 template <typename real, typename acc_t>
 size_t tile_lds_bytes(const Geom& g, int max_chunks);
 
+// Per-step record of section 2 Eq. 4, summed by the push kernels while they
+// push: the three spin sums and the count of the selected particles (one
+// species, or -1 for all; with window set, kinetic energy in [emin, emax)
+// MeV, evaluated as the on-demand reduction does), each workgroup adding its
+// sums into slot (workgroup index mod kRecSlots) of acc, kRecStride doubles
+// a slot; the host adds the slots up.
+constexpr int kRecSlots = 32;
+constexpr int kRecStride = 4;
+struct RecArgs {
+    double* acc;   // nullptr: no record
+    int species;
+    int window;
+    double emin, emax;
+    double mu[kMaxSpecies];
+};
+
 template <typename real, typename acc_t, int DIM>
 hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,
                              const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
-                             const Fields<freal>& f, int deposit, hipStream_t stream);
+                             const Fields<freal>& f, int deposit, const RecArgs& rec, hipStream_t stream);
 
 // 3D push marching along z over runs of R tiles of one tile column (field
 // and current guard planes carried between the tiles of a run); T[2] >= 3.
@@ -24,8 +40,8 @@ hipError_t launch_push_march(const Geom& g, const Consts<real>& k, const PArrays
 
 template <typename real, int DIM>
 hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
-                             int32_t* ctr, const Fields<freal>& f, int deposit, int blocks,
-                             hipStream_t stream);
+                             int32_t* ctr, const Fields<freal>& f, int deposit, const RecArgs& rec,
+                             int blocks, hipStream_t stream);
 
 template <typename real, int DIM>
 hipError_t launch_insert(const Geom& g, const PArrays<real>& p, const Segs& seg,

@@ -57,6 +57,43 @@ struct GlobalJ {
     }
 };
 
+// Per-step Eq. 4 record: a pushed particle's contribution, if selected.
+template <typename real>
+__device__ inline void rec_accumulate(const RecArgs& rec, int sp, const real u[3], const real s[3],
+                                      double (&racc)[4]) {
+    if (rec.species >= 0 && sp != rec.species) return;
+    if (rec.window) {
+        const double ux = u[0], uy = u[1], uz = u[2];
+        const double gamma = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        const double ek = rec.mu[sp] * (gamma - 1.0) * kMeC2MeV;
+        if (!(ek >= rec.emin && ek < rec.emax)) return;
+    }
+    racc[0] += (double)s[0];
+    racc[1] += (double)s[1];
+    racc[2] += (double)s[2];
+    racc[3] += 1.0;
+}
+
+// The workgroup's record sums added into its slot.  Every thread calls it.
+__device__ inline void rec_add_block(double (&racc)[4], double* slot) {
+    __shared__ double part[kBlock / 64][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = racc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (lane == 0) part[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w][threadIdx.x];
+        if (t != 0.0) atomicAdd(slot + threadIdx.x, t);
+    }
+}
+
 constexpr int kPairCap = 256;   // compaction pairs per round
 constexpr int kStageRows = 4;   // field rows a thread loads before storing them
 
@@ -125,11 +162,13 @@ __device__ inline void copy_particle(const PArrays<real>& from, long long i, con
 // previous tile's carried sums and only the others start at zero; jkeep = 3
 // when the last three current planes (local z = T-1 .. T+1) are kept in
 // shared memory for the next tile instead of being added to global J.
-template <typename real, typename acc_t, int DIM>
+// With REC, the pushed particles of the tile are also summed into the
+// step's Eq. 4 record (rec).
+template <typename real, typename acc_t, int DIM, bool REC = false>
 __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Consts<real>& k, const PArrays<real>& p, const Segs& seg,
                           const PArrays<real>& lv, int32_t* __restrict__ ctr, int slot, const Fields<freal>& f,
                           int deposit, int t, int sid_base, int inst_tag, int fz0 = 0, int jz0 = 0,
-                          int jkeep = 0) {
+                          int jkeep = 0, const RecArgs& rec = RecArgs{}) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_nleave, s_lbase;
     int tc[3];
@@ -238,6 +277,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
     const real half_dt = real(0.5) * k.dt;
 
     const int wave = threadIdx.x >> 6;
+    double racc[4] = {0.0, 0.0, 0.0, 0.0};
     const uint32_t dummy_i = (uint32_t)(seg.dummy + lane) * 4u;
     const uint32_t dummy_r = (uint32_t)(seg.dummy + lane) * (uint32_t)sizeof(real);
 
@@ -262,7 +302,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
             const real wgt = w_n;
             if (base + kBlock < n) load(start, min(i + kBlock, n - 1));
 
-            bool leave = false, bad = false;
+            bool leave = false, bad = false, gone = false;
             int newcell = cell0;
             if (active) {
                 int c[3];
@@ -319,6 +359,11 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
                     }
                     newcell = dead ? kDeadCell : pack_cell<DIM>(nc[0], nc[1], nc[2]);
                     leave = leave || dead;
+                    gone = dead;
+                }
+                // a particle that left the box is not in the step's ensemble
+                if constexpr (REC) {
+                    if (!gone) rec_accumulate(rec, sp, u, s, racc);
                 }
             }
 
@@ -429,6 +474,7 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
         if (threadIdx.x == 0) seg.count[sid] = n - L;
         __syncthreads();
     }
+    if constexpr (REC) rec_add_block(racc, rec.acc + (blockIdx.x % kRecSlots) * kRecStride);
 
     if (deposit) {
         __syncthreads();
@@ -461,10 +507,10 @@ __device__ __attribute__((always_inline)) void push_tile(const Geom& g, const Co
     }
 }
 
-template <typename real, typename acc_t, int DIM>
+template <typename real, typename acc_t, int DIM, bool REC>
 __global__ void __launch_bounds__(kBlock)
 k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
-             int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit) {
+             int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit, RecArgs rec) {
     // the other step's leaver counter is free again: clear it for the next step
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
     // tiles in launch order: workgroups are dealt round-robin over the 8
@@ -473,7 +519,7 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     // giving each XCD a contiguous range of its own measured slower
     const int t = (int)blockIdx.x;
     if (t >= g.ntiles) return;
-    push_tile<real, acc_t, DIM>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0);
+    push_tile<real, acc_t, DIM, REC>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0, 0, 0, 0, rec);
 }
 
 // 3D push marching along z (an alternative to k_push_tiles that moves fewer
@@ -539,9 +585,10 @@ k_push_march(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
 // One particle of the overflow store (species sp): gather from and deposit
 // into the global fields of its run.
 // Returns true when the pushed momentum or spin is not finite.
-template <typename real, int DIM>
+template <typename real, int DIM, bool REC = false>
 __device__ inline bool push_stash_one(const Geom& g, const Consts<real>& k, const PArrays<real>& st, int i,
-                                      int sp, const Fields<freal>& f, int deposit) {
+                                      int sp, const Fields<freal>& f, int deposit,
+                                      const RecArgs& rec = RecArgs{}, double* racc = nullptr) {
     const int32_t cell = st.cell[i];
     if (cell == kDeadCell) return false;   // left the box earlier
     GlobalFields<freal, DIM> GF;
@@ -612,6 +659,9 @@ __device__ inline bool push_stash_one(const Geom& g, const Consts<real>& k, cons
         }
     }
     st.cell[i] = dead ? kDeadCell : pack_cell<DIM>(nc[0], nc[1], nc[2]);
+    if constexpr (REC) {
+        if (!dead) rec_accumulate(rec, sp, u, s, *reinterpret_cast<double(*)[4]>(racc));
+    }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) st.off[a][i] = o[a];
 #pragma unroll
@@ -622,15 +672,17 @@ __device__ inline bool push_stash_one(const Geom& g, const Consts<real>& k, cons
     return !__builtin_isfinite(dot3(u, u) + dot3(s, s));
 }
 
-template <typename real, int DIM>
+template <typename real, int DIM, bool REC>
 __global__ void __launch_bounds__(kBlock)
 k_push_stash(Geom g, Consts<real> k, PArrays<real> st, int32_t* __restrict__ ctr,
-             Fields<freal> f, int deposit) {
+             Fields<freal> f, int deposit, RecArgs rec) {
     const int n = ctr[CTR_STASH];
     bool bad = false;
+    double racc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-        bad = push_stash_one<real, DIM>(g, k, st, i, st.sp[i], f, deposit) || bad;
+        bad = push_stash_one<real, DIM, REC>(g, k, st, i, st.sp[i], f, deposit, rec, racc) || bad;
     if (bad) ctr[CTR_NONFINITE] = 1;
+    if constexpr (REC) rec_add_block(racc, rec.acc + (blockIdx.x % kRecSlots) * kRecStride);
 }
 
 // Positions for the active lanes of a wavefront that each add 1 to
@@ -971,11 +1023,20 @@ hipError_t launch_repack_segments(const PArrays<real>& from, const PArrays<real>
 template <typename real, typename acc_t, int DIM>
 hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays<real>& p,
                              const Segs& seg, const PArrays<real>& lv, int32_t* ctr, int slot,
-                             const Fields<freal>& f, int deposit, hipStream_t stream) {
+                             const Fields<freal>& f, int deposit, const RecArgs& rec, hipStream_t stream) {
     const size_t lds = tile_lds_bytes<real, acc_t>(g, seg.max_chunks);
     const int grid = ((g.ntiles + 7) >> 3) * 8;
-    hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM>), dim3(grid), dim3(kBlock), lds, stream,
-                       g, k, p, seg, lv, ctr, slot, f, deposit);
+    if constexpr (!kFixedAcc<acc_t>) {
+        if (rec.acc) {
+            hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM, true>), dim3(grid), dim3(kBlock), lds, stream,
+                               g, k, p, seg, lv, ctr, slot, f, deposit, rec);
+            return hipGetLastError();
+        }
+    } else {
+        if (rec.acc) return hipErrorInvalidValue;   // the record is not kept in the deterministic mode
+    }
+    hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM, false>), dim3(grid), dim3(kBlock), lds, stream,
+                       g, k, p, seg, lv, ctr, slot, f, deposit, rec);
     return hipGetLastError();
 }
 
@@ -994,10 +1055,14 @@ hipError_t launch_push_march(const Geom& g, const Consts<real>& k, const PArrays
 
 template <typename real, int DIM>
 hipError_t launch_push_stash(const Geom& g, const Consts<real>& k, const PArrays<real>& st,
-                             int32_t* ctr, const Fields<freal>& f, int deposit,
+                             int32_t* ctr, const Fields<freal>& f, int deposit, const RecArgs& rec,
                              int blocks, hipStream_t stream) {
-    hipLaunchKernelGGL((k_push_stash<real, DIM>), dim3(blocks), dim3(kBlock), 0, stream,
-                       g, k, st, ctr, f, deposit);
+    if (rec.acc)
+        hipLaunchKernelGGL((k_push_stash<real, DIM, true>), dim3(blocks), dim3(kBlock), 0, stream,
+                           g, k, st, ctr, f, deposit, rec);
+    else
+        hipLaunchKernelGGL((k_push_stash<real, DIM, false>), dim3(blocks), dim3(kBlock), 0, stream,
+                           g, k, st, ctr, f, deposit, rec);
     return hipGetLastError();
 }
 
@@ -1080,7 +1145,7 @@ template int push_batch_blocks_per_cu<double, double>(size_t);
 #define SPINPIC_INST_PUSH(real, acc, DIM)                                                       \
     template hipError_t launch_push_tiles<real, acc, DIM>(const Geom&, const Consts<real>&,    \
         const PArrays<real>&, const Segs&, const PArrays<real>&, int32_t*, int,                \
-        const Fields<freal>&, int, hipStream_t);
+        const Fields<freal>&, int, const RecArgs&, hipStream_t);
 
 SPINPIC_INST_PUSH(float, float, 2)
 SPINPIC_INST_PUSH(float, float, 3)
@@ -1111,7 +1176,8 @@ template size_t tile_lds_bytes<double, double>(const Geom&, int);
 
 #define SPINPIC_INST_REST(real, DIM)                                                            \
     template hipError_t launch_push_stash<real, DIM>(const Geom&, const Consts<real>&,         \
-        const PArrays<real>&, int32_t*, const Fields<freal>&, int, int, hipStream_t);          \
+        const PArrays<real>&, int32_t*, const Fields<freal>&, int, const RecArgs&, int,         \
+        hipStream_t);                                                                          \
     template hipError_t launch_insert<real, DIM>(const Geom&, const PArrays<real>&,            \
         const Segs&, const PArrays<real>&, const PArrays<real>&, int32_t*, int,                 \
         unsigned long long*, int, hipStream_t);

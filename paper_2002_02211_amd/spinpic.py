@@ -28,7 +28,8 @@ PIC_FLAG_CELL_ROWS = 4
 MAX_SPECIES = 4
 PIC_MAX_SPECTRUM_BINS = 1024
 FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho")
-EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_fields", "pic_particles",
+EXPORTED = ("pic_init", "pic_step", "pic_polarization", "pic_polarization_record",
+            "pic_polarization_history", "pic_fields", "pic_particles",
             "pic_spectrum", "pic_spectrum_noalloc", "pic_phase_space", "pic_density", "pic_energy", "pic_stats",
             "pic_particles_cells", "pic_test_poison",
             "pic_window", "pic_timing", "pic_timing_read", "pic_last_error", "pic_free",
@@ -111,6 +112,9 @@ def load_library(path=LIB_PATH):
     lib.pic_step.argtypes = [P, ctypes.c_int32]
     lib.pic_polarization.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.pic_polarization_record.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32]
+    lib.pic_polarization_history.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.pic_fields.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]
     lib.pic_particles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64)]
@@ -305,6 +309,24 @@ def pic_polarization(ctx, species=-1, ekin_min_mev=-math.inf, ekin_max_mev=math.
     return P, int(N.value)
 
 
+PIC_MAX_RECORD_STEPS = 65536
+
+
+def pic_polarization_record(ctx, species=-1, ekin_min_mev=-math.inf, ekin_max_mev=math.inf, capacity=1024):
+    _check(load_library().pic_polarization_record(ctx, int(species), float(ekin_min_mev), float(ekin_max_mev),
+                                                  int(capacity)), ctx)
+
+
+def pic_polarization_history(ctx, cap):
+    """(P, N): the recorded steps' mean spins, shape (n, 3), and counts, shape (n,)."""
+    P = np.zeros((max(int(cap), 1), 3))
+    N = np.zeros(max(int(cap), 1), dtype=np.int64)
+    n = ctypes.c_int32()
+    _check(load_library().pic_polarization_history(ctx, _dptr(P), N.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                   int(cap), ctypes.byref(n)), ctx)
+    return P[:n.value].copy(), N[:n.value].copy()
+
+
 def pic_fields(ctx, mask, cells):
     ncomp = bin(int(mask)).count("1")
     out = np.empty(ncomp * cells)
@@ -437,6 +459,15 @@ class Simulation:
 
     def polarization(self, species=-1, emin=-math.inf, emax=math.inf):
         return pic_polarization(self.ctx, species, emin, emax)
+
+    def record_polarization(self, species=-1, emin=-math.inf, emax=math.inf, capacity=1024):
+        """Start a per-step Eq. 4 record of `capacity` steps (0: stop)."""
+        pic_polarization_record(self.ctx, species, emin, emax, capacity)
+        self._rec_cap = int(capacity)
+
+    def polarization_history(self):
+        """The recorded steps since the last call: P (n, 3) and N (n,)."""
+        return pic_polarization_history(self.ctx, getattr(self, "_rec_cap", 0))
 
     def fields(self, names=FIELD_NAMES):
         mask = 0

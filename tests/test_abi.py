@@ -160,6 +160,9 @@ def test_T16_calls_on_null_context(lib):
     assert lib.pic_phase_space(None, 0, 0, 0.0, 1.0, 4, 0, -1.0, 1.0, 4, None) == S.PIC_ESTATE
     assert lib.pic_density(None, 0, None, 0) == S.PIC_ESTATE
     assert lib.pic_window(None, ctypes.byref(S.window_config())) == S.PIC_ESTATE
+    n = ctypes.c_int32(7)
+    assert lib.pic_polarization_record(None, -1, 0.0, 1.0, 16) == S.PIC_ESTATE
+    assert lib.pic_polarization_history(None, None, None, 0, ctypes.byref(n)) == S.PIC_ESTATE
     lib.pic_free(None)
 
 

@@ -1,0 +1,126 @@
+"""The per-step record of section 2 Eq. 4 (pic_polarization_record /
+pic_polarization_history) on the GPU.
+
+The push kernels sum the selected particles' spins as they push them; the
+record of a step must then be what pic_polarization returns after that step
+(the same state, FP64 sums in another order: the counts equal, the means to
+rounding), the overflow store's particles included, and, in FP64, what the
+oracle's Eq. 4 gives after every step.  Inputs are the seeded synthetic
+plasmas of ``synth``.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2002_02211_amd import spinpic as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+CASES = [
+    ("small2d", "fp64", -1, -math.inf, math.inf),
+    ("small2d", "fp32", 0, 0.0, 0.05),
+    ("small2d", "fp32", 1, 0.0, 0.01),
+    ("small3d", "fp32", -1, -math.inf, math.inf),
+    ("small3d", "fp64", 0, 0.01, 1e6),
+]
+
+
+@pytest.mark.parametrize("preset,precision,species,emin,emax", CASES)
+def test_record_is_polarization_after_every_step(preset, precision, species, emin, emax):
+    _say("record vs pic_polarization", preset, precision, species, emin, emax)
+    spec = synth.preset(preset)
+    state = synth.make_state(spec)
+    sim = S.Simulation(S.config_from_spec(spec, precision=precision), state["particles"], state["fields"])
+    sim.record_polarization(species, emin, emax, capacity=16)
+    want = []
+    for _ in range(12):
+        sim.step(1)
+        want.append(sim.polarization(species, emin, emax))
+    P, N = sim.polarization_history()
+    assert P.shape == (12, 3) and N.shape == (12,)
+    for k, (p, n) in enumerate(want):
+        assert N[k] == n, (k, N[k], n)
+        np.testing.assert_allclose(P[k], p, rtol=0.0, atol=1e-13, err_msg="step %d" % k)
+    assert N.max() > 0
+    # read out: the record is empty until the next steps
+    P2, N2 = sim.polarization_history()
+    assert N2.size == 0
+    sim.step(3)
+    P3, N3 = sim.polarization_history()
+    assert N3.size == 3
+    sim.close()
+
+
+def test_record_matches_oracle_with_overflow_store():
+    """FP64, every step against the oracle's Eq. 4; a fast beam into tiles
+    with no spare room sends particles through the overflow store (pushed by
+    its own kernel, which adds its particles to the record too)."""
+    _say("record vs oracle, overflow store")
+    spec = synth.preset("small2d", n=(64, 32, 1))
+    state = synth.make_state(spec)
+    e = state["particles"][0]
+    left = e[:, 0] < 0.5 * spec["n"][0] * spec["d"][0]
+    e[left, 3] = 3.0
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp64", slack=1e-6), state["particles"], state["fields"])
+    ref = oracle.Sim(spec, state)
+    sim.record_polarization(-1, capacity=40)
+    overflow = 0
+    want = []
+    for _ in range(30):
+        sim.step(1)
+        ref.step(1)
+        overflow = max(overflow, sim.stats()["overflow"])
+        want.append(ref.polarization(-1))
+    P, N = sim.polarization_history()
+    assert overflow > 0
+    for k, (p, n) in enumerate(want):
+        assert N[k] == n
+        np.testing.assert_allclose(P[k], p, rtol=0.0, atol=1e-9, err_msg="step %d" % k)
+    sim.close()
+
+
+def test_record_capacity_and_arguments():
+    _say("record capacity and arguments")
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp32"), state["particles"], state["fields"])
+    # no record kept: nothing to read
+    P, N = sim.polarization_history()
+    assert N.size == 0
+    sim.record_polarization(-1, capacity=4)
+    sim.step(4)
+    with pytest.raises(S.PicError) as ei:
+        sim.step(1)
+    assert ei.value.code == S.PIC_ECAPACITY
+    P, N = S.pic_polarization_history(sim.ctx, 4)
+    assert N.size == 4
+    sim.step(2)
+    with pytest.raises(S.PicError) as ei:
+        S.pic_polarization_history(sim.ctx, 1)   # room for fewer steps than recorded
+    assert ei.value.code == S.PIC_EINVAL
+    for bad in ((5, -math.inf, math.inf, 8), (-1, math.nan, 1.0, 8), (-1, 0.0, 1.0, -1),
+                (-1, 0.0, 1.0, S.PIC_MAX_RECORD_STEPS + 1)):
+        with pytest.raises(S.PicError) as ei:
+            S.pic_polarization_record(sim.ctx, *bad)
+        assert ei.value.code == S.PIC_EINVAL
+    sim.record_polarization(-1, capacity=0)   # stop
+    sim.step(10)
+    P, N = sim.polarization_history()
+    assert N.size == 0
+    sim.close()
+    # the deterministic mode keeps no record
+    det = S.Simulation(S.config_from_spec(spec, precision="fp64", deterministic=True), state["particles"],
+                       state["fields"])
+    with pytest.raises(S.PicError) as ei:
+        det.record_polarization(-1, capacity=8)
+    assert ei.value.code == S.PIC_EINVAL
+    det.close()
