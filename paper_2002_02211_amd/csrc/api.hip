@@ -744,7 +744,7 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
     }
     ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
     moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
-    acc_ = (double*)dalloc(8 * sizeof(double));
+    acc_ = (double*)dalloc(kRedSlots * kRedStride * sizeof(double));
     rho_ = (double*)dalloc(g_.ncells * sizeof(double));
     ref_ = (double*)dalloc(g_.ncells * sizeof(double));
     resid_blocks_ = (int)std::min<long long>(4096, (g_.ncells + kBlock - 1) / kBlock);
@@ -1026,10 +1026,15 @@ Status Engine<real, DIM>::repack() {
 
 template <typename real, int DIM>
 Status Engine<real, DIM>::reduce(int mode, const ReduceArgs& ra, double* host_acc) {
-    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+    double h[kRedSlots * kRedStride];
+    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, sizeof h, stream_));
     HIP_OR_FAIL((launch_reduce_particles<real, DIM>(mode, g_, p_, seg_, st_, ctr_, ra, acc_, rho_, stream_)));
-    HIP_OR_FAIL(hipMemcpyAsync(host_acc, acc_, 8 * sizeof(double), hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(h, acc_, sizeof h, hipMemcpyDeviceToHost, stream_));
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    for (int q = 0; q < kRedStride; ++q) {
+        host_acc[q] = 0.0;
+        for (int s = 0; s < kRedSlots; ++s) host_acc[q] += h[s * kRedStride + q];
+    }
     return Status{};
 }
 
@@ -2036,7 +2041,7 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     ctr_ = (int32_t*)dalloc(CTR_NCTR * sizeof(int32_t));
     moved_ = (unsigned long long*)dalloc(sizeof(unsigned long long));
     run_ns_ = (unsigned long long*)dalloc(nrun * sizeof(unsigned long long));
-    acc_ = (double*)dalloc(8 * sizeof(double));
+    acc_ = (double*)dalloc(kRedSlots * kRedStride * sizeof(double));
     d_runs_ = (RunDesc<real>*)dalloc(nrun * sizeof(RunDesc<real>));
     d_order_ = (TileRef*)dalloc(ntiles_ * sizeof(TileRef));
     d_blk_run_ = (int32_t*)dalloc((size_t)yee_nblk_ * sizeof(int32_t));
@@ -2342,11 +2347,14 @@ Status BatchEngine<real>::polarization(int run, int species, double emin, double
     view.start = seg_.start + R.sid_base;
     view.cap = seg_.cap + R.sid_base;
     view.count = seg_.count + R.sid_base;
-    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, 8 * sizeof(double), stream_));
+    double h[kRedSlots * kRedStride];
+    HIP_OR_FAIL(hipMemsetAsync(acc_, 0, sizeof h, stream_));
     HIP_OR_FAIL((launch_reduce_particles<real, 2>(RED_POLARIZATION, R.g, p_, view, st_, ctr_, ra, acc_, nullptr, stream_)));
-    double acc[8];
-    HIP_OR_FAIL(hipMemcpyAsync(acc, acc_, sizeof acc, hipMemcpyDeviceToHost, stream_));
+    HIP_OR_FAIL(hipMemcpyAsync(h, acc_, sizeof h, hipMemcpyDeviceToHost, stream_));
     HIP_OR_FAIL(hipStreamSynchronize(stream_));
+    double acc[kRedStride] = {};
+    for (int q = 0; q < kRedStride; ++q)
+        for (int s = 0; s < kRedSlots; ++s) acc[q] += h[s * kRedStride + q];
     *N = (int64_t)std::llround(acc[3]);
     for (int a = 0; a < 3; ++a) P[a] = acc[3] > 0 ? acc[a] / acc[3] : 0.0;
     return Status{};

@@ -525,7 +525,67 @@ k_reduce_particles(int mode, Geom g, PArrays<real> p, Segs seg, PArrays<real> st
             reduce_one<real, DIM>(mode, st, i, tag % kMaxSpecies, g, ra, v, rho);
         }
     }
-    if (mode != RED_RHO) block_sum_add<4>(v, acc);
+    if (mode != RED_RHO) block_sum_add<4>(v, acc + (blockIdx.x % kRedSlots) * kRedStride);
+}
+
+// Charge density of the tile particles (RED_RHO): one workgroup per
+// segment adds its particles' CIC weights into a shared-memory node tile
+// (nodes org .. org + T along each axis), then adds the non-zero nodes to rho
+// (periodic wrap; beyond an open x face dropped).  One global add per node
+// and segment instead of 2^DIM per particle.
+template <typename real, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_rho_tiles(Geom g, PArrays<real> p, Segs seg, ReduceArgs ra, double* rho) {
+    extern __shared__ double rl[];
+    const int sid = blockIdx.x;
+    const int sp = sid % g.nsp;
+    if (ra.species >= 0 && sp != ra.species) return;
+    const int n = seg.count[sid];
+    if (n == 0) return;
+    const int t = sid / g.nsp;
+    const int org[3] = {(t % g.nt[0]) * g.T[0], ((t / g.nt[0]) % g.nt[1]) * g.T[1],
+                        DIM == 3 ? (t / (g.nt[0] * g.nt[1])) * g.T[2] : 0};
+    const int Nx = g.T[0] + 1, Ny = g.T[1] + 1, Nz = DIM == 3 ? g.T[2] + 1 : 1;
+    const int N = Nx * Ny * Nz;
+    for (int k = threadIdx.x; k < N; k += kBlock) rl[k] = 0.0;
+    __syncthreads();
+    const long long start = seg.start[sid];
+    const double Z = ra.Z[sp];
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        int c[3];
+        unpack_cell<DIM>(p.cell[start + i], c[0], c[1], c[2]);
+        const double q = Z * (double)p.w[start + i];
+        double o[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < DIM; ++a) o[a] = (double)p.off[a][start + i];
+        const int base = ((DIM == 3 ? c[2] - org[2] : 0) * Ny + (c[1] - org[1])) * Nx + (c[0] - org[0]);
+#pragma unroll
+        for (int corner = 0; corner < (1 << DIM); ++corner) {
+            double wgt = q;
+            int off = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const int up = (corner >> a) & 1;
+                wgt *= up ? o[a] : 1.0 - o[a];
+                off += up ? (a == 0 ? 1 : (a == 1 ? Nx : Nx * Ny)) : 0;
+            }
+            atomicAdd(&rl[base + off], wgt);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += kBlock) {
+        const double v = rl[k];
+        if (v == 0.0) continue;
+        int ix = org[0] + k % Nx;
+        int iy = org[1] + (k / Nx) % Ny;
+        int iz = DIM == 3 ? org[2] + k / (Nx * Ny) : 0;
+        if (ix >= g.n[0]) {
+            if (g.open_x) continue;   // beyond an open x face
+            ix -= g.n[0];
+        }
+        if (iy >= g.n[1]) iy -= g.n[1];
+        if (DIM == 3 && iz >= g.n[2]) iz -= g.n[2];
+        atomicAdd(rho + ((long long)iz * g.n[1] + iy) * g.n[0] + ix, v);
+    }
 }
 
 // ---- deterministic mode
@@ -837,6 +897,14 @@ hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>&
                                    const ReduceArgs& ra, double* acc, double* rho,
                                    hipStream_t stream) {
     const int nseg = g.ntiles * g.nsp;
+    if (mode == RED_RHO) {
+        // tile particles through shared-memory node tiles, then the overflow store
+        const size_t lds = (size_t)(g.T[0] + 1) * (g.T[1] + 1) * (DIM == 3 ? g.T[2] + 1 : 1) * sizeof(double);
+        hipLaunchKernelGGL((k_rho_tiles<real, DIM>), dim3(nseg), dim3(kBlock), lds, stream, g, p, seg, ra, rho);
+        hipLaunchKernelGGL((k_reduce_particles<real, DIM>), dim3(64), dim3(kBlock), 0, stream,
+                           mode, g, p, seg, st, ctr, ra, acc, rho, 0);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_reduce_particles<real, DIM>), dim3(nseg + 64), dim3(kBlock), 0, stream,
                        mode, g, p, seg, st, ctr, ra, acc, rho, nseg);
     return hipGetLastError();

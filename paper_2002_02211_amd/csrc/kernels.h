@@ -163,6 +163,13 @@ struct ReduceArgs {
     double Z[kMaxSpecies];
 };
 
+// The particle reductions add workgroup w's sums into slot w mod kRedSlots of
+// acc (kRedStride doubles a slot), so that the adds of tens of thousands of
+// workgroups do not all go to the same few addresses; the caller clears
+// kRedSlots * kRedStride doubles and adds the slots up.
+constexpr int kRedSlots = 32;
+constexpr int kRedStride = 8;
+
 template <typename real, int DIM>
 hipError_t launch_reduce_particles(int mode, const Geom& g, const PArrays<real>& p,
                                    const Segs& seg, const PArrays<real>& st, const int32_t* ctr,
