@@ -64,8 +64,19 @@ __device__ inline V3<real> cross(V3<real> a, V3<real> b) {
     return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-// sine and cosine of one angle with one range reduction
-__device__ inline void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+// Sine and cosine of one angle.  FP32: the angle is reduced to r in
+// [-pi, pi] by the nearest whole turn k (Cody and Waite's two-constant
+// reduction: 2 pi = 6.28125 + 1.9353071795864769e-3, whose first part times
+// k is exact for |k| < 2^16), and the hardware sine and cosine, which take
+// their argument in turns, get r / (2 pi).
+__device__ inline void sin_cos(float x, float* s, float* c) {
+    const float k = rintf(x * 0.159154943f);
+    float r = fmaf(-k, 6.28125f, x);
+    r = fmaf(-k, 1.9353071795864769e-3f, r);
+    const float turns = r * 0.159154943f;
+    *s = __builtin_amdgcn_sinf(turns);
+    *c = __builtin_amdgcn_cosf(turns);
+}
 __device__ inline void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
 
 // Every intermediate of one step that its adjoint needs.
