@@ -33,6 +33,12 @@ namespace spinpic {
 // arithmetic, which the refinement would only lengthen.
 __device__ inline float trecip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double trecip(double x) { return 1.0 / x; }
+// Square root of 1 + u.u (>= 1): FP32 takes the hardware v_sqrt_f32 (about
+// 1 ulp) instead of the correctly rounded sequence (scaling for tiny
+// arguments and two correction steps, some fifteen instructions), for the
+// same reason as above.
+__device__ inline float tsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double tsqrt(double x) { return sqrt(x); }
 
 template <typename real>
 struct V3 {
@@ -99,7 +105,7 @@ __device__ inline void step_values(const TrackParams<real>& P, V3<real> x, V3<re
     v.B = v3(real(-0.25) * v.A * x.y, real(0.25) * v.A * x.x, real(0));
     // Boris: half kick, rotation by the Cayley map, half kick
     v.um = u + P.eps * v.E;
-    v.gm = sqrt(real(1) + dot(v.um, v.um));
+    v.gm = tsqrt(real(1) + dot(v.um, v.um));
     v.ig = trecip(v.gm);
     v.tv = (P.eps * v.ig) * v.B;
     v.f = real(2) * trecip(real(1) + dot(v.tv, v.tv));
@@ -118,7 +124,7 @@ __device__ inline void step_values(const TrackParams<real>& P, V3<real> x, V3<re
     v.fs = real(2) * trecip(real(1) + dot(v.tau, v.tau));
     v.sp1 = s + cross(s, v.tau);
     // move
-    v.gn = sqrt(real(1) + dot(v.un, v.un));
+    v.gn = tsqrt(real(1) + dot(v.un, v.un));
     v.ign = trecip(v.gn);
 }
 
