@@ -124,3 +124,31 @@ def test_record_capacity_and_arguments():
         det.record_polarization(-1, capacity=8)
     assert ei.value.code == S.PIC_EINVAL
     det.close()
+
+
+def test_record_with_moving_window():
+    """With a moving window the record of a step without a shift is
+    pic_polarization after it; at a shift the removed and injected
+    particles enter from the next step (the record counts the particles the
+    step pushed and kept)."""
+    import test_gpu_window as W
+    _say("record with a moving window")
+    spec = synth.preset("small2d")
+    state = synth.make_state(spec)
+    sim = S.Simulation(S.config_from_spec(spec, precision="fp64"), state["particles"], state["fields"])
+    sim.window(**W._win(shift_cells=16, ppc=2, n0=0.03))
+    sim.record_polarization(-1, capacity=64)
+    shifts, want = [], []
+    for _ in range(40):
+        before = sim.stats()["shifts"]
+        sim.step(1)
+        shifts.append(sim.stats()["shifts"] != before)
+        want.append(sim.polarization(-1))
+    P, N = sim.polarization_history()
+    assert any(shifts) and not all(shifts)
+    for k, ((p, n), shifted) in enumerate(zip(want, shifts)):
+        if shifted:
+            continue
+        assert N[k] == n, (k, N[k], n)
+        np.testing.assert_allclose(P[k], p, rtol=0.0, atol=1e-13, err_msg="step %d" % k)
+    sim.close()
