@@ -7,6 +7,8 @@ dt = 0.95 of the Courant limit, run for 200 steps.  This script calls only
 (steps 100 and 200): polarization (all species and per species), energies,
 256 particles per species (192 drawn at random plus the 64 with the largest
 |u|, the ones most sensitive to rounding) and 256 random field values.  Also
+stored: the polarization of all species after every step (P_t, N_t: Eq. 4
+over the whole ensemble, steps 1 .. 200).  Also
 stored, at step 100: the same particles from the oracle run with float32
 particle storage (state rounded to float32 after every step), which bounds
 what any float32 particle store must deviate from the float64 run.
@@ -41,9 +43,14 @@ def main():
            "snapshots": {}}
     dumps = {}
     step = 0
+    P_t, N_t = [], []
     for target in SNAPSHOTS:
-        sim.step(target - step)
-        step = target
+        while step < target:
+            sim.step(1)
+            step += 1
+            P, N = sim.polarization()
+            P_t.append([float(v) for v in P])
+            N_t.append(int(N))
         snap = {"P_all": list(sim.polarization()[0]), "N_all": sim.polarization()[1],
                 "P_species": [list(sim.polarization(k)[0]) for k in range(2)],
                 "energy": list(sim.energy()), "particles": {}}
@@ -63,6 +70,8 @@ def main():
         dumps["F_%d" % target] = F
         out["snapshots"][str(target)] = snap
         print("step", target, "P", snap["P_all"], "energy", snap["energy"], flush=True)
+    out["P_t"] = P_t
+    out["N_t"] = N_t
     sim32 = oracle.Sim(spec, state, store_fp32=True)
     sim32.step(100)
     out["store_fp32"] = {"100": {}}

@@ -3,10 +3,12 @@ the FP64 oracle's run stored in tests/golden/c1_oracle.json (written by
 tests/golden/make_c1_golden.py, which calls only the oracle).
 
 * FP64: sampled particles to 1e-9 (position in cells, momentum relative to
-  max(|u|, u_thermal), spin), polarization to 1e-12, energies to 1e-9,
-  sampled field values to 1e-9 of the component's scale, div E - rho held.
-* FP32-mixed: the mean polarization vector to 1e-3 over the full 200-step
-  run; per particle after 100 steps, 1e-5 or at most 3x the error of the
+  max(|u|, u_thermal), spin), polarization to 1e-12 at the snapshots and,
+  through the per-step record, after every one of the 200 steps, energies
+  to 1e-9, sampled field values to 1e-9 of the component's scale, div E -
+  rho held.
+* FP32-mixed: the mean polarization vector to 1e-3 after every step of the
+  200-step run; per particle after 100 steps, 1e-5 or at most 3x the error of the
   oracle run with float32 particle storage (electrons quivering in the a0 = 3
   pulse amplify every rounding of their stored state).
 """
@@ -55,6 +57,7 @@ def test_c1_fp64_matches_oracle_run(golden, c1):
     spec, state = c1
     _say("c1 fp64 200 steps")
     sim = S.Simulation(S.config_from_spec(spec, precision="fp64"), state["particles"], state["fields"])
+    sim.record_polarization(-1, capacity=200)
     step = 0
     for key in ("100", "200"):
         snap = golden["snapshots"][key]
@@ -79,6 +82,13 @@ def test_c1_fp64_matches_oracle_run(golden, c1):
         scale = {nm: max(np.max(np.abs(F[nm])), 1e-30) for nm in names[:9]}
         for (c, z, y, x), v in zip(snap["field_cells"], snap["field_values"]):
             assert abs(F[names[c]][z, y, x] - v) <= 1e-9 * scale[names[c]], (names[c], z, y, x)
+    # P(t) after every step, from the record the push kernels kept
+    Pt, Nt = sim.polarization_history()
+    assert Pt.shape == (200, 3)
+    np.testing.assert_array_equal(Nt, np.array(golden["N_t"]))
+    dPt = np.max(np.abs(Pt - np.array(golden["P_t"])))
+    _say("P(t) over 200 steps, max |dP| %.2e" % dPt)
+    assert dPt < 1e-12
     sim.close()
 
 
@@ -86,6 +96,7 @@ def test_c1_fp32_within_stated_bounds(golden, c1):
     spec, state = c1
     _say("c1 fp32 200 steps")
     sim = S.Simulation(S.config_from_spec(spec, precision="fp32"), state["particles"], state["fields"])
+    sim.record_polarization(-1, capacity=200)
     sim.step(100)
     snap = golden["snapshots"]["100"]
     for k in range(2):
@@ -108,4 +119,9 @@ def test_c1_fp32_within_stated_bounds(golden, c1):
     for k in range(2):
         Pk, _ = sim.polarization(k)
         assert np.max(np.abs(Pk - np.array(snap["P_species"][k]))) <= 1e-3
+    Pt, Nt = sim.polarization_history()
+    np.testing.assert_array_equal(Nt, np.array(golden["N_t"]))
+    dPt = np.max(np.abs(Pt - np.array(golden["P_t"])), axis=1)
+    _say("P(t) over 200 steps, max |dP| %.2e (step %d)" % (dPt.max(), int(np.argmax(dPt)) + 1))
+    assert dPt.max() <= 1e-3
     sim.close()
