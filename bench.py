@@ -643,6 +643,10 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
     out["stats_timed"] = sim.stats()
     out["P_timed"], _ = sim.polarization()
     if full_steps:
+        # Eq. 4 of every later step, kept by the push kernels (P(t) for the
+        # FP32-against-FP64 comparison over the run)
+        sim.record_polarization(-1, capacity=full_steps)
+        out["P_t_from_step"] = done + 1
         if done < sample_step:
             sim.step(sample_step - done)
             done = sample_step
@@ -664,6 +668,8 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
         if late["push_deposit"][1] != left:
             raise SystemExit("bench: %d push launches in the last %d steps" % (late["push_deposit"][1], left))
         done = full_steps
+        out["P_t"], out["N_t"] = sim.polarization_history()
+        sim.record_polarization(-1, capacity=0)
         print("[bench] %s %s: %d further steps in %.2f s" % (spec["name"], precision, left, out["rest_elapsed"]),
               file=sys.stderr, flush=True)
     st = sim.stats()
@@ -722,6 +728,11 @@ def compare_runs(spec, r32, r64):
            "self_check": {"steps_fp32": int(r32["stats"]["steps"]), "steps_fp64": int(r64["stats"]["steps"]),
                           "distinct_contexts": r32["ctx"] != r64["ctx"] or r32["ctx"] == 0,
                           "P_bitwise_identical": bool(np.array_equal(P32, P64))}}
+    if "P_t" in r32 and "P_t" in r64 and len(r32["P_t"]) == len(r64["P_t"]) and len(r32["P_t"]):
+        d = np.max(np.abs(np.asarray(r32["P_t"]) - np.asarray(r64["P_t"])), axis=1)
+        res["dP_over_run"] = {"from_step": r32["P_t_from_step"], "to_step": r32["steps_done"],
+                              "max": float(d.max()), "at_step": int(r32["P_t_from_step"] + int(np.argmax(d))),
+                              "bound": 1e-3, "bound_met": bool(d.max() <= 1e-3)}
     if "sample" in r32:
         per = {}
         for k, sp in enumerate(spec["species"]):
@@ -951,7 +962,8 @@ def full_run_summary(r, npart):
             "pushes_per_s": npart * r["rest_steps"] / r["rest_elapsed"],
             "push_avg_launch_ms": push_ms / max(push_n, 1),
             "overflow_particles_at_end": st["overflow"], "repacks": st["repacks"],
-            "particles_moved_tile": st["moved"], "P_end": [float(v) for v in r["P"]]}
+            "particles_moved_tile": st["moved"], "P_end": [float(v) for v in r["P"]],
+            "per_step_polarization_record": "on (from step %d)" % r.get("P_t_from_step", 0)}
 
 
 def bench_other(S, workload, args, compare):
