@@ -994,6 +994,10 @@ def bench_other(S, workload, args, compare):
         out["note"] = "c1's 20 MB of state stays in the 256 MB last-level cache: absolute pushes/s only"
         out["roofline"]["frac"] = None
         out["roofline"]["fp64_grid"]["frac"] = None
+    if not args.no_cpu_baseline:
+        # the oracle on one thread over a bounded sample of this workload
+        # (no forked workers here: this process already holds the GPU)
+        out["cpu_baseline_one_thread"] = cpu_baseline(spec, state, 500000 if workload == "c3" else 131072)
     if compare and precision == "fp32":
         r64 = run_schedule(S, spec, state, "fp64", S.PIC_ACC_DEFAULT, args.warmup, args.steps,
                            full_steps=spec["steps"])
