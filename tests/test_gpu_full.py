@@ -1,6 +1,7 @@
 """Full-size parity: the c2 and c3 workloads at their real sizes, in the launch
 configuration bench.py times (default tiles, FP32 particles, FP64 shared-memory
-current sums), plus c2 on the FP64 path.
+current sums), plus c2 and c3 on the FP64 path (the reference the FP32 runs
+are compared with over their full length).
 
 The oracle cannot run these whole, so one step (after three warm-up steps, so
 that rebinning has happened) is checked piece by piece from the GPU's own
@@ -119,7 +120,7 @@ def _patch_current(pos, parts1, spec, grid, lo, size, margin=3):
 # holding x = (cell + offset) * dx: at 4096 cells its last bit is ~7e-13 of a
 # cell, which enters the oracle's shape-factor differences.
 CASES = [("c2", "fp32", 1e-5, 1e-6, 1e-12), ("c2", "fp64", 1e-11, 1e-11, 1e-12),
-         ("c3", "fp32", 1e-5, 1e-6, 1e-12)]
+         ("c3", "fp32", 1e-5, 1e-6, 1e-12), ("c3", "fp64", 1e-11, 1e-11, 1e-12)]
 
 
 @pytest.mark.timeout(600)
