@@ -209,7 +209,7 @@ def test_single_particle_current_sums_T9():
 
 
 @pytest.mark.parametrize("case", ["empty_species", "one_particle", "tiny_grid", "odd_tiles",
-                                  "big_tile", "tile_3d_4", "boundary_crossers"])
+                                  "big_tile", "tile_3d_4", "boundary_crossers", "max_x_2d", "max_z_3d"])
 def test_edge_cases_fp64(case):
     _say("edge case", case)
     if case in ("empty_species", "one_particle", "tiny_grid", "odd_tiles", "big_tile",
@@ -220,7 +220,30 @@ def test_edge_cases_fp64(case):
     kw = {}
     if case == "tiny_grid":
         spec = synth.preset("small2d", n=(3, 2, 1))
+    if case == "max_x_2d":
+        # the largest 2D extent the packed cell word holds along x (16 bits),
+        # with a ragged last tile (65535 = 4095 x 16 + 15)
+        spec = synth.preset("small2d", n=(65535, 4, 1))
+    if case == "max_z_3d":
+        # the largest 3D extent along z (10 bits), ragged last tile
+        spec = synth.preset("small3d", n=(8, 8, 1023))
     state = synth.make_state(spec)
+    if case in ("max_x_2d", "max_z_3d"):
+        # a few thousand particles, a quarter of them fast and next to the
+        # periodic faces of the long axis, moving out through them
+        ax = 0 if case == "max_x_2d" else 2
+        L = spec["n"][ax] * spec["d"][ax]
+        rng = np.random.default_rng(5)
+        parts = []
+        for arr in state["particles"]:
+            sub = arr[rng.choice(arr.shape[0], 2048, replace=False)].copy()
+            m = sub.shape[0] // 8
+            sub[:m, ax] = L - 1e-3 * spec["d"][ax]
+            sub[:m, 3 + ax] = 5.0
+            sub[m:2 * m, ax] = 1e-3 * spec["d"][ax]
+            sub[m:2 * m, 3 + ax] = -5.0
+            parts.append(sub)
+        state["particles"] = parts
     if case == "empty_species":
         state["particles"][1] = np.zeros((0, 10))
     if case == "one_particle":
