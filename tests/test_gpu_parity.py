@@ -209,7 +209,8 @@ def test_single_particle_current_sums_T9():
 
 
 @pytest.mark.parametrize("case", ["empty_species", "one_particle", "tiny_grid", "odd_tiles",
-                                  "big_tile", "tile_3d_4", "boundary_crossers", "max_x_2d", "max_z_3d"])
+                                  "big_tile", "tile_3d_4", "boundary_crossers", "max_x_2d", "max_x_3d",
+                                  "max_y_3d", "max_z_3d"])
 def test_edge_cases_fp64(case):
     _say("edge case", case)
     if case in ("empty_species", "one_particle", "tiny_grid", "odd_tiles", "big_tile",
@@ -225,13 +226,18 @@ def test_edge_cases_fp64(case):
         # with a ragged last tile (65535 = 4095 x 16 + 15)
         spec = synth.preset("small2d", n=(65535, 4, 1))
     if case == "max_z_3d":
-        # the largest 3D extent along z (10 bits), ragged last tile
+        # the largest 3D extents: 11 bits along x and y, 10 along z; ragged
+        # last tiles
         spec = synth.preset("small3d", n=(8, 8, 1023))
+    if case == "max_x_3d":
+        spec = synth.preset("small3d", n=(2047, 12, 2))
+    if case == "max_y_3d":
+        spec = synth.preset("small3d", n=(12, 2047, 2))
     state = synth.make_state(spec)
-    if case in ("max_x_2d", "max_z_3d"):
+    if case.startswith("max_"):
         # a few thousand particles, a quarter of them fast and next to the
         # periodic faces of the long axis, moving out through them
-        ax = 0 if case == "max_x_2d" else 2
+        ax = {"max_x_2d": 0, "max_x_3d": 0, "max_y_3d": 1, "max_z_3d": 2}[case]
         L = spec["n"][ax] * spec["d"][ax]
         rng = np.random.default_rng(5)
         parts = []
