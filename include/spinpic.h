@@ -153,8 +153,9 @@ int pic_init(const pic_config* cfg, const pic_state* init, const pic_allocator* 
  * failed context, PIC_EHIP when a launch fails, PIC_ECAPACITY when particle
  * storage is exhausted, PIC_ENONFINITE when the push has produced a NaN or
  * infinite momentum or spin: every push kernel probes its particles and sets
- * a device flag, which the host reads every 16 steps (when it waits for the
- * stream anyway) and before every read-back call. */
+ * a device flag, which the host reads every 16 steps (every 4 while the
+ * overflow store is large; it waits for the stream then anyway) and before
+ * every read-back call. */
 int pic_step(pic_ctx* ctx, int32_t nsteps);
 
 /* Section 2 Eq. 4: mean spin of the particles of one species (species = -1:
@@ -262,7 +263,7 @@ int pic_particles_cells(pic_ctx* ctx, int32_t species, double* host_out, size_t 
  * of `species` (the first one of the first non-empty tile) with a NaN.  The
  * next pic_step's push then produces a non-finite state, which the probe in
  * the push kernel records: pic_step returns PIC_ENONFINITE at its next check
- * (every 16 steps) and the read-back calls return it at once.  Returns
+ * (every 16 steps at the latest) and the read-back calls return it at once.  Returns
  * PIC_EINVAL when the species has no particle in a tile.  Waits. */
 int pic_test_poison(pic_ctx* ctx, int32_t species);
 

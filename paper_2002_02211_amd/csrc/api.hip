@@ -73,6 +73,26 @@ Status scratch_address(int dev, double** out) {
     return Status{};
 }
 
+// Overflow policy.  Every kStashCheck steps the step loop waits for its
+// stream, so that the pinned copy of the overflow count is current (the host
+// can otherwise run many steps ahead of the GPU), and folds the overflow
+// store back into the tiles when it holds more than npart / kStashFrac
+// particles, or any at all on a kStashPeriod boundary: overflow particles are
+// pushed from global memory at a fraction of the tile push's rate.  While the
+// store holds more than a quarter of that, the next check comes after
+// kStashCheckSoon steps instead (a laser-compressed plasma can fill it by
+// several times the threshold within 16 steps); checks stay on multiples of
+// their interval, so every kStashPeriod boundary is one.
+constexpr int kStashCheck = 16;
+constexpr int kStashCheckSoon = 4;
+constexpr int kStashPeriod = 64;
+constexpr long long kStashFrac = 512;
+constexpr int kStashBlocks = 1024;
+// A segment that overflowed is usually in a region still being compressed
+// (a laser's ponderomotive front): the repack gives it kGrowSlack times the
+// slack and keeps room it was given while the count stays within that.
+constexpr double kGrowSlack = 3.0;
+
 // ---------------------------------------------------------------- config
 
 struct Resolved {
@@ -386,6 +406,7 @@ private:
     long long count_sp_[kMaxSpecies] = {0, 0, 0, 0};
     double d_[3] = {1, 1, 1};
     int64_t nstep_ = 0;
+    int64_t check_at_ = kStashCheck;   // step of the next overflow check
     int64_t repacks_ = 0;
 
     PArrays<real> p_{}, lv_{}, st_{};
@@ -493,20 +514,13 @@ static long long seg_capacity(long long count, double slack) {
 // traffic, so the single-tile push stays the default.
 constexpr int kMarchRun = 1;
 
-// Overflow policy.  Every kStashCheck steps the step loop waits for its
-// stream, so that the pinned copy of the overflow count is current (the host
-// can otherwise run many steps ahead of the GPU), and folds the overflow
-// store back into the tiles when it holds more than npart / kStashFrac
-// particles, or any at all on a kStashPeriod boundary: overflow particles are
-// pushed from global memory at a fraction of the tile push's rate.
-constexpr int kStashCheck = 16;
-constexpr int kStashPeriod = 64;
-constexpr long long kStashFrac = 512;
-constexpr int kStashBlocks = 1024;
-// A segment that overflowed is usually in a region still being compressed
-// (a laser's ponderomotive front): the repack gives it kGrowSlack times the
-// slack and keeps room it was given while the count stays within that.
-constexpr double kGrowSlack = 3.0;
+
+// The step of the next overflow check after one at nstep that found nstash
+// particles in the overflow store (none left if it repacked).
+static long long next_check(long long nstep, long long nstash, long long npart) {
+    const long long every = nstash > std::max(256LL, npart / (4 * kStashFrac)) ? kStashCheckSoon : kStashCheck;
+    return (nstep / every + 1) * every;
+}
 
 static bool repack_due(long long nstep, long long nstash, long long npart) {
     if (nstash <= 0) return false;
@@ -864,15 +878,18 @@ Status Engine<real, DIM>::step(int nsteps) {
         if (rec_on_ && rec_n_ >= rec_cap_)
             return fail(PIC_ECAPACITY, "the polarization record is full (%d steps): read it with "
                         "pic_polarization_history", rec_cap_);
-        if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
+        if (nstep_ > 0 && nstep_ == check_at_) {
             HIP_OR_FAIL(hipStreamSynchronize(stream_));
             if (h_ctr_[CTR_NONFINITE])
                 return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin before step %lld",
                             (long long)nstep_);
-            if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
+            long long left = h_ctr_[CTR_STASH];
+            if (repack_due(nstep_, left, npart_)) {
                 Status S = repack();
                 if (S.code) return S;
+                left = 0;
             }
+            check_at_ = next_check(nstep_, left, npart_);
         }
         const int slot = (int)(nstep_ & 1);
         // the step's slot of the Eq. 4 record, if one is kept
@@ -932,7 +949,7 @@ Status Engine<real, DIM>::step(int nsteps) {
         }
         // the overflow count for the next check (read only there: a copy
         // every step would cost a transfer and two launch gaps per step)
-        if ((nstep_ + 1) % kStashCheck == 0)
+        if (nstep_ + 1 == check_at_)
             HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, 2 * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
@@ -1795,6 +1812,7 @@ private:
     int use_acc64_ = 1, deposit_ = 1;
     long long cap_total_ = 0, npart_ = 0, ncells_ = 0;
     int64_t nstep_ = 0, repacks_ = 0;
+    int64_t check_at_ = kStashCheck;   // step of the next overflow check
     int push_blocks_ = 1;
     PArrays<real> p_{}, lv_{}, st_{};
     Segs seg_{};
@@ -2206,15 +2224,18 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
 template <typename real>
 Status BatchEngine<real>::step(int nsteps) {
     for (int it = 0; it < nsteps; ++it) {
-        if (nstep_ > 0 && nstep_ % kStashCheck == 0) {
+        if (nstep_ > 0 && nstep_ == check_at_) {
             HIP_OR_FAIL(hipStreamSynchronize(stream_));
             if (h_ctr_[CTR_NONFINITE])
                 return fail(PIC_ENONFINITE, "a push produced a non-finite momentum or spin before step %lld",
                             (long long)nstep_);
-            if (repack_due(nstep_, h_ctr_[CTR_STASH], npart_)) {
+            long long left = h_ctr_[CTR_STASH];
+            if (repack_due(nstep_, left, npart_)) {
                 Status S = repack();
                 if (S.code) return S;
+                left = 0;
             }
+            check_at_ = next_check(nstep_, left, npart_);
         }
         const int slot = (int)(nstep_ & 1);
         const int jnext = jcur_ ^ 1;
@@ -2250,7 +2271,7 @@ Status BatchEngine<real>::step(int nsteps) {
             timer_stop(timer_, stream_, 3);
         }
         // the overflow count for the next check only
-        if ((nstep_ + 1) % kStashCheck == 0)
+        if (nstep_ + 1 == check_at_)
             HIP_OR_FAIL(hipMemcpyAsync(h_ctr_ + CTR_STASH, ctr_ + CTR_STASH, 2 * sizeof(int32_t),
                                        hipMemcpyDeviceToHost, stream_));
         if (deposit_) jcur_ = jnext;
