@@ -436,7 +436,13 @@ __device__ inline int shape_pair(real o0, real o1, int dc, real S0[3], real S1[3
 // three nodes vanishes), so that along an axis the particle does not cross
 // every entry on node 2 is exactly zero.  The eight (2D) or twelve (3D)
 // entries that can be nonzero without a crossing are added for every lane;
-// the others only by lanes that changed cell.
+// the others only by lanes that changed cell.  In 3D a particle that changed
+// cell along one axis e only has eight more nonzero entries: J_e one node
+// further along e (4), and J_f, J_g on node 2 along e (2 each; f, g the other
+// axes).  With a sink that takes linear offsets (Sink::kStrided) such lanes
+// add just these eight, the axis picked per lane; lanes that crossed two or
+// three axes add all 42.  (The same in 2D, five entries instead of 13, made
+// the memory-bound 2D push slower.)
 template <typename real, int DIM, class Sink>
 __device__ inline void esirkepov(const real S0[3][3], const real S1[3][3], const int dc[3],
                                  const real q[3], real qz2d, Sink& sink) {
@@ -486,13 +492,15 @@ __device__ inline void esirkepov(const real S0[3][3], const real S1[3][3], const
         }
         return;
     }
-    // 3D: J_a(k, jb, jc) = q_a C_a[k] (S0b[jb] h_c[jc] + DSb[jb] g_c[jc]),
-    // b, c the axes after a in cyclic order
+    // 3D: J_a(k, jb, jc) = q_a C_a[k] T_a(jb, jc) with the transverse factor
+    // T_a(jb, jc) = S0b[jb] h_c[jc] + DSb[jb] g_c[jc], b, c the axes after a
+    // in cyclic order
+    real T[3][2][2], qa0[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int b = (a + 1) % 3;
         const int c = (a + 2) % 3;
-        const real qa = q[a] * C[a][0];
+        qa0[a] = q[a] * C[a][0];
 #pragma unroll
         for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
@@ -501,11 +509,47 @@ __device__ inline void esirkepov(const real S0[3][3], const real S1[3][3], const
                 idx[a] = 0;
                 idx[b] = jb;
                 idx[c] = jc;
-                sink.add(a, idx[0], idx[1], idx[2],
-                         qa * (S0[b][jb] * h[c][jc] + DS[b][jb] * gq[c][jc]));
+                T[a][jb][jc] = S0[b][jb] * h[c][jc] + DS[b][jb] * gq[c][jc];
+                sink.add(a, idx[0], idx[1], idx[2], qa0[a] * T[a][jb][jc]);
             }
     }
-    if (crossed) {
+    if (!crossed) return;
+    bool all42 = true;
+    if constexpr (Sink::kStrided) {
+        const int nx = (dc[0] != 0) + (dc[1] != 0) + (dc[2] != 0);
+        all42 = nx > 1;
+        if (nx == 1) {
+            // the crossed axis e, and f = e + 1, g = e + 2 (cyclic): pk picks
+            // the value belonging to e from the ones for e = 0, 1, 2
+            const bool x0 = dc[0] != 0, x1 = dc[1] != 0;
+            auto pk = [&](auto v0, auto v1, auto v2) { return x0 ? v0 : (x1 ? v1 : v2); };
+            const real qe1 = pk(q[0] * C[0][1], q[1] * C[1][1], q[2] * C[2][1]);
+            const real qf0 = pk(qa0[1], qa0[2], qa0[0]);
+            const real qg0 = pk(qa0[2], qa0[0], qa0[1]);
+            const real S0e = pk(S0[0][2], S0[1][2], S0[2][2]), DSe = pk(DS[0][2], DS[1][2], DS[2][2]);
+            const real he = pk(h[0][2], h[1][2], h[2][2]), gqe = pk(gq[0][2], gq[1][2], gq[2][2]);
+            const int Se = pk(sink.stride(0), sink.stride(1), sink.stride(2));
+            const int Sf = pk(sink.stride(1), sink.stride(2), sink.stride(0));
+            const int Sg = pk(sink.stride(2), sink.stride(0), sink.stride(1));
+            const int ce = pk(sink.comp(0), sink.comp(1), sink.comp(2)) + Se;
+            const int cf = pk(sink.comp(1), sink.comp(2), sink.comp(0)) + 2 * Se;
+            const int cg = pk(sink.comp(2), sink.comp(0), sink.comp(1)) + 2 * Se;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // J_e one node further along e: the core's T_e times C_e[1]
+#pragma unroll
+                for (int jc = 0; jc < 2; ++jc)
+                    sink.add_off(ce + j * Sf + jc * Sg, qe1 * pk(T[0][j][jc], T[1][j][jc], T[2][j][jc]));
+                // J_f (b = g, c = e) at node j along g, 2 along e
+                const real S0g = pk(S0[2][j], S0[0][j], S0[1][j]), DSg = pk(DS[2][j], DS[0][j], DS[1][j]);
+                sink.add_off(cf + j * Sg, qf0 * (S0g * he + DSg * gqe));
+                // J_g (b = e, c = f) at node 2 along e, j along f
+                const real hf = pk(h[1][j], h[2][j], h[0][j]), gqf = pk(gq[1][j], gq[2][j], gq[0][j]);
+                sink.add_off(cg + j * Sf, qg0 * (S0e * hf + DSe * gqf));
+            }
+        }
+    }
+    if (all42) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int b = (a + 1) % 3;

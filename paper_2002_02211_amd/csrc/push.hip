@@ -16,11 +16,19 @@ struct TileJ {
     int Hx, Hxy, H;
     int o;   // offset of the stencil's base node
     double fscale;
+    static constexpr bool kStrided = true;
+    __device__ inline int stride(int a) const { return a == 0 ? 1 : (a == 1 ? Hx : Hxy); }
+    __device__ inline int comp(int c) const { return c * H; }
+    // v to J at offset off (comp(c) plus node offsets) from the base node
     template <typename real>
-    __device__ inline void add(int c, int i, int j, int k, real v) const {
-        acc_t* q = base + c * H + o + (DIM == 3 ? k * Hxy : 0) + j * Hx + i;
+    __device__ inline void add_off(int off, real v) const {
+        acc_t* q = base + o + off;
         if constexpr (kFixedAcc<acc_t>) atomicAdd(q, to_fixed((double)v, fscale));
         else atomicAdd(q, (acc_t)v);
+    }
+    template <typename real>
+    __device__ inline void add(int c, int i, int j, int k, real v) const {
+        add_off(c * H + (DIM == 3 ? k * Hxy : 0) + j * Hx + i, v);
     }
     // The entries the stencil reaches only when the particle changed cell:
     // added without testing for zero (in the tile, a branch per entry cost
@@ -36,6 +44,7 @@ struct TileJ {
 // fixed-point integers during the push (see to_fixed).
 template <typename freal, int DIM>
 struct GlobalJ {
+    static constexpr bool kStrided = false;
     freal* J[3];
     int n[3];
     int b[3];  // absolute base node
