@@ -208,6 +208,81 @@ def test_single_particle_current_sums_T9():
     sim.close()
 
 
+def _crossing_state(spec, rng, n, patterns):
+    """Particles that change cell along exactly the axes of their pattern
+    (a tuple of 0/1 per axis) in one step through zero fields: offset 0.03
+    or 0.97 of a cell and a move of 0.06 cells toward the near edge on the
+    crossing axes, offset in [0.3, 0.7] and a move of at most 0.05 cells on
+    the others."""
+    d, dt = spec["d"], spec["dt"]
+    rows = np.zeros((n, 10))
+    for i in range(n):
+        cross = patterns[rng.integers(len(patterns))]
+        v = np.zeros(3)
+        for a in range(3):
+            cell = rng.integers(spec["n"][a])
+            if cross[a]:
+                up = rng.random() < 0.5
+                o, step = (0.97, 0.06) if up else (0.03, -0.06)
+            else:
+                o, step = rng.uniform(0.3, 0.7), rng.uniform(-0.05, 0.05)
+            rows[i, a] = (cell + o) * d[a]
+            v[a] = step * d[a] / dt
+        rows[i, 3:6] = v / math.sqrt(1.0 - v @ v)
+        sv = rng.normal(size=3)
+        rows[i, 6:9] = sv / np.linalg.norm(sv)
+        rows[i, 9] = rng.uniform(0.5, 1.5)
+    return rows
+
+
+@pytest.mark.parametrize("precision,tile,which", [("fp64", None, "mixed"), ("fp64", (8, 6, 4), "mixed"),
+                                                  ("fp64", (8, 6, 4), "one_axis"),
+                                                  ("fp32", None, "mixed"), ("fp32", None, "one_axis")])
+def test_3d_current_by_crossed_axes(precision, tile, which):
+    """The 3D deposit takes one branch for lanes that crossed one axis (the
+    8 extra entries of that axis, picked per lane) and another for lanes
+    that crossed two or three; a wavefront holds lanes of every kind.  The
+    current after one step through zero fields, against the oracle node by
+    node and against its closed form (sum of J_a = sum of Z w dx_a / dt,
+    section 2's charge-conserving deposit)."""
+    _say("3d current by crossed axes", precision, tile, which)
+    spec = {"ndim": 3, "n": (24, 12, 12), "d": (0.3, 0.4, 0.35), "dt": 0.1,
+            "species": [{"Z": -1.0, "mu": 1.0, "a": 0.0}]}
+    one = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    patterns = one if which == "one_axis" else one + [(0, 0, 0), (1, 1, 0), (0, 1, 1), (1, 0, 1), (1, 1, 1)]
+    rows = _crossing_state(spec, np.random.default_rng(2024), 4000, patterns)
+    state = {"particles": [rows], "fields": np.zeros((6, 12, 12, 24))}
+    kw = {} if tile is None else {"tile": tile}
+    sim = S.Simulation(S.config_from_spec(spec, precision=precision, **kw), state["particles"],
+                       state["fields"])
+    # the FP32 path starts from the state rounded as it stores it
+    if precision == "fp32":
+        state = fp32_rounded_state(spec, state)
+        rows = state["particles"][0]
+    ref = oracle.Sim(spec, state)
+    sim.step(1)
+    ref.step(1)
+    F = sim.fields(("Jx", "Jy", "Jz"))
+    Fo = ref.fields()
+    out = sim.particles(0)
+    L = np.array(spec["n"]) * np.array(spec["d"])
+    disp = out[:, 1:4] - rows[:, 0:3]
+    disp -= L * np.round(disp / L)      # through the periodic faces
+    moved_cells = np.abs(disp) / np.array(spec["d"])
+    assert moved_cells.max() < 0.07
+    jmax = max(np.abs(F[nm]).max() for nm in ("Jx", "Jy", "Jz"))
+    # sums: relative to the sum of |terms| (the net sum cancels); nodes:
+    # relative to max |J| (FP32: shape-factor differences of ~0.06 cells
+    # computed in float32)
+    tol_sum, tol_node = (1e-12, 1e-13) if precision == "fp64" else (1e-6, 1e-5)
+    for a, nm in enumerate(("Jx", "Jy", "Jz")):
+        terms = -rows[:, 9] * disp[:, a] / spec["dt"]
+        assert abs(np.sum(F[nm]) - np.sum(terms)) <= tol_sum * np.sum(np.abs(terms)), nm
+        err = np.abs(F[nm] - Fo[6 + a]).max() / jmax
+        assert err <= tol_node, "%s: %.3e of max |J|" % (nm, err)
+    sim.close()
+
+
 @pytest.mark.parametrize("case", ["empty_species", "one_particle", "tiny_grid", "odd_tiles",
                                   "big_tile", "tile_3d_4", "boundary_crossers", "max_x_2d", "max_x_3d",
                                   "max_y_3d", "max_z_3d"])
