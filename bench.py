@@ -616,6 +616,9 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
     import torch
     out = {"precision": precision}
     cfg = S.config_from_spec(spec, precision=precision, deposit_acc=acc, tile=tile, slack=slack)
+    # device memory the caching allocator holds at most during this run (its
+    # cache included: what earlier runs of this process left cached counts)
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.time()
     sim = S.Simulation(cfg, state["particles"], state["fields"])
     if window:
@@ -670,8 +673,9 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
         done = full_steps
         out["P_t"], out["N_t"] = sim.polarization_history()
         sim.record_polarization(-1, capacity=0)
-        print("[bench] %s %s: %d further steps in %.2f s" % (spec["name"], precision, left, out["rest_elapsed"]),
-              file=sys.stderr, flush=True)
+        print("[bench] %s %s: %d further steps in %.2f s (%d repacks; allocator holds %.1f GB at most)"
+              % (spec["name"], precision, left, out["rest_elapsed"], sim.stats()["repacks"],
+                 torch.cuda.max_memory_reserved() / 1e9), file=sys.stderr, flush=True)
     st = sim.stats()
     if st["steps"] != done:
         raise SystemExit("bench: the context counted %d steps, the schedule %d" % (st["steps"], done))
@@ -681,9 +685,15 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
     out["ctx"] = sim.ctx.value or 0
     if on_open is not None:
         out["extra"] = on_open(sim)
+    out["reserved_gb_peak"] = torch.cuda.max_memory_reserved() / 1e9
     sim.close()
     del sim
     torch.cuda.synchronize()
+    # hand the freed stores back to the device, so that the next run of this
+    # process starts as a run in a fresh process would (the c3 FP64 push over
+    # its later steps took 19.6 ms after four runs' cached blocks, 11.2 ms in
+    # a process of its own)
+    torch.cuda.empty_cache()
     return out
 
 
@@ -963,7 +973,8 @@ def full_run_summary(r, npart):
             "push_avg_launch_ms": push_ms / max(push_n, 1),
             "overflow_particles_at_end": st["overflow"], "repacks": st["repacks"],
             "particles_moved_tile": st["moved"], "P_end": [float(v) for v in r["P"]],
-            "per_step_polarization_record": "on (from step %d)" % r.get("P_t_from_step", 0)}
+            "per_step_polarization_record": "on (from step %d)" % r.get("P_t_from_step", 0),
+            "allocator_reserved_gb_peak": r["reserved_gb_peak"]}
 
 
 def bench_other(S, workload, args, compare):

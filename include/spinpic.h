@@ -131,7 +131,11 @@ typedef struct {
                               NULL starts from zero fields */
 } pic_state;
 
-/* Optional device allocator; alloc returns NULL on failure. */
+/* Optional device allocator; alloc returns NULL on failure.  A repack
+ * allocates the new particle store (one array per particle field) before it
+ * frees the old one; a store that must grow gets a quarter more slots than
+ * it needs, and otherwise the size of the current one, so that a caching
+ * allocator can serve each repack from the arrays the previous one freed. */
 typedef struct {
     void* (*alloc)(void* user, size_t bytes);
     void (*free)(void* user, void* ptr);

@@ -402,6 +402,7 @@ private:
     double fx_inv_ = 0.0;          // 1 / the fixed-point current's scale
     int nseg_ = 0;
     long long cap_total_ = 0;
+    long long store_slots_ = 0;   // slots allocated in p_ (at least cap_total_ + kSpareSlots)
     long long npart_ = 0;
     long long count_sp_[kMaxSpecies] = {0, 0, 0, 0};
     double d_[3] = {1, 1, 1};
@@ -501,6 +502,17 @@ static long long round_up(long long v, long long m) { return (v + m - 1) / m * m
 // with a 32-bit byte offset, so 2^29 slots at most.
 constexpr long long kMaxSlots = (1LL << 29) - 64;
 constexpr long long kSpareSlots = 64;   // write targets of masked-off lanes
+
+// Slots to allocate for the store a repack builds, `need` of them used: the
+// current store's size while that suffices, else a quarter more than needed.
+// The repack fills the new store from the old one and only then frees it, so
+// with a caching allocator (torch's) the block the previous repack freed
+// serves this one; sizes that grew a little at every repack would each take
+// a new block and leave all the older ones cached.
+static long long store_alloc_slots(long long need, long long current) {
+    if (need <= current) return current;
+    return std::min(need + need / 4, kMaxSlots + kSpareSlots);
+}
 
 static long long seg_capacity(long long count, double slack) {
     return round_up((long long)std::ceil(count * (1.0 + slack)) + 32, 32);
@@ -735,7 +747,8 @@ Status Engine<real, DIM>::init(const Resolved& R, const pic_state* st) {
         Status A = scratch_address(dev_, &spec_buf_);
         if (A.code) return A;
     }
-    Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
+    store_slots_ = cap_total_ + kSpareSlots;
+    Status S = alloc_store(p_, store_slots_, false);
     if (S.code) return S;
     store_cap_ = std::max(npart_, 1LL);
     S = alloc_store(lv_, store_cap_, true);
@@ -1013,7 +1026,8 @@ Status Engine<real, DIM>::repack() {
         if (L.code) return L;
     }
     PArrays<real> np{};
-    Status S = alloc_store(np, total + kSpareSlots, false);
+    const long long slots = store_alloc_slots(total + kSpareSlots, store_slots_);
+    Status S = alloc_store(np, slots, false);
     if (S.code) return S;
     int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     if (!d_nstart) return fail(PIC_ENOMEM, "repack allocation failed");
@@ -1029,6 +1043,7 @@ Status Engine<real, DIM>::repack() {
     free_store(p_);
     dfree(d_nstart);
     p_ = np;
+    store_slots_ = slots;
     cap_total_ = total;
     seg_.dummy = (int)total;
     {
@@ -1811,6 +1826,7 @@ private:
     int nsp_ = 0, nseg_ = 0, ntiles_ = 0;
     int use_acc64_ = 1, deposit_ = 1;
     long long cap_total_ = 0, npart_ = 0, ncells_ = 0;
+    long long store_slots_ = 0;   // slots allocated in p_ (at least cap_total_ + kSpareSlots)
     int64_t nstep_ = 0, repacks_ = 0;
     int64_t check_at_ = kStashCheck;   // step of the next overflow check
     int push_blocks_ = 1;
@@ -2037,7 +2053,8 @@ Status BatchEngine<real>::init(const std::vector<Resolved>& Rs, const pic_state*
     if (push_lds() > 64 * 1024) return fail(PIC_ECAPACITY, "a tile needs more than 64 KiB of shared memory");
 
     // ---- device memory
-    Status S = alloc_store(p_, cap_total_ + kSpareSlots, false);
+    store_slots_ = cap_total_ + kSpareSlots;
+    Status S = alloc_store(p_, store_slots_, false);
     if (S.code) return S;
     S = alloc_store(lv_, std::max(npart_, 1LL), true);
     if (S.code) return S;
@@ -2327,7 +2344,8 @@ Status BatchEngine<real>::repack() {
         if (lds > 64 * 1024) return fail(PIC_ECAPACITY, "a tile segment needs more than 64 KiB of shared memory");
     }
     PArrays<real> np{};
-    Status S = alloc_store(np, total + kSpareSlots, false);
+    const long long slots = store_alloc_slots(total + kSpareSlots, store_slots_);
+    Status S = alloc_store(np, slots, false);
     if (S.code) return S;
     int32_t* d_nstart = (int32_t*)dalloc(nseg_ * sizeof(int32_t));
     if (!d_nstart) return fail(PIC_ENOMEM, "repack allocation failed");
@@ -2341,6 +2359,7 @@ Status BatchEngine<real>::repack() {
     free_store(p_);
     dfree(d_nstart);
     p_ = np;
+    store_slots_ = slots;
     cap_total_ = total;
     seg_.dummy = (int)total;
     seg_.max_chunks = (int)((maxcap + 63) / 64);
