@@ -204,3 +204,35 @@ def test_full_size_one_step(workload, precision, ptol, jtol, ftol):
     for c, nm in enumerate(("Bx", "By", "Bz")):
         sc = max(np.max(np.abs(B0[c])), 1e-30)
         assert np.max(np.abs(F1[nm] - B0[c])) <= ftol * sc, nm
+
+
+def test_c2_full_run_repacks_reuse_allocator_blocks():
+    """c2 FP32 over its whole run (about 20 repacks as the laser compresses
+    the plasma) through torch's caching allocator, the binding's default: a
+    repack frees the old store after building the new one, and the memory
+    the allocator holds must stay within a few stores, not grow by a store
+    at every repack (which had filled a whole device in one process)."""
+    import torch
+    _say("c2 full run, allocator")
+    spec = synth.preset("c2")
+    state = synth.make_state(spec)
+    npart = sum(p.shape[0] for p in state["particles"])
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sim = S.Simulation(S.config_from_spec(spec), state["particles"], state["fields"])
+    del state
+    torch.cuda.synchronize()
+    at_init = torch.cuda.memory_reserved()
+    torch.cuda.reset_peak_memory_stats()
+    sim.step(spec["steps"])
+    torch.cuda.synchronize()
+    st = sim.stats()
+    grown = torch.cuda.max_memory_reserved() - at_init
+    # one FP32 2D store: cell, two offsets, u, s, w, id (44 B a slot) for the
+    # particles and the 25 % slack
+    store = npart * 1.25 * 44
+    _say("repacks %d, allocator grew by %.1f GB (%.1f stores)" % (st["repacks"], grown / 1e9, grown / store))
+    sim.close()
+    torch.cuda.empty_cache()
+    assert st["repacks"] >= 10
+    assert grown <= 4 * store
