@@ -160,7 +160,7 @@ def write_traffic(fetch_csv, write_csv, workload, precision, probe_mib=1024):
     f_fetch = probe / (cf_mean * cf_n)
     f_write = probe / write[fill[0]][0]
     # the push without the per-step Eq. 4 record (the bench also runs the one with it)
-    push = [k for k in fetch if "k_push_tiles" in k and "true>" not in k]
+    push = [k for k in fetch if "k_push_tiles" in k and "k_push_tiles_rec" not in k and "true>" not in k]
     if len(push) != 1:
         raise SystemExit("expected one push kernel instantiation, found %s" % push)
     pf, n_f = fetch[push[0]]

@@ -531,6 +531,21 @@ k_push_tiles(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv
     push_tile<real, acc_t, DIM, REC>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0, 0, 0, 0, rec);
 }
 
+// The push that also keeps the Eq. 4 record: the same kernel, held to two
+// waves per SIMD (256 registers at most).  The FP64 3D one took 264 without
+// the cap, one wave per SIMD, which doubled its time; the others stay below
+// it.  A kernel of its own, so that the cap leaves the code of the push
+// without the record as it is.
+template <typename real, typename acc_t, int DIM>
+__global__ void __launch_bounds__(kBlock, 2)
+k_push_tiles_rec(Geom g, Consts<real> k, PArrays<real> p, Segs seg, PArrays<real> lv,
+                 int32_t* __restrict__ ctr, int slot, Fields<freal> f, int deposit, RecArgs rec) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[slot ^ 1] = 0;
+    const int t = (int)blockIdx.x;
+    if (t >= g.ntiles) return;
+    push_tile<real, acc_t, DIM, true>(g, k, p, seg, lv, ctr, slot, f, deposit, t, 0, 0, 0, 0, 0, rec);
+}
+
 // 3D push marching along z (an alternative to k_push_tiles that moves fewer
 // guard bytes; measured no faster on c3, see the engine's kMarchRun):
 // workgroup w takes a run of up to R tiles of one
@@ -1037,7 +1052,7 @@ hipError_t launch_push_tiles(const Geom& g, const Consts<real>& k, const PArrays
     const int grid = ((g.ntiles + 7) >> 3) * 8;
     if constexpr (!kFixedAcc<acc_t>) {
         if (rec.acc) {
-            hipLaunchKernelGGL((k_push_tiles<real, acc_t, DIM, true>), dim3(grid), dim3(kBlock), lds, stream,
+            hipLaunchKernelGGL((k_push_tiles_rec<real, acc_t, DIM>), dim3(grid), dim3(kBlock), lds, stream,
                                g, k, p, seg, lv, ctr, slot, f, deposit, rec);
             return hipGetLastError();
         }
