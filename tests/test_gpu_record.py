@@ -152,3 +152,32 @@ def test_record_with_moving_window():
         assert N[k] == n, (k, N[k], n)
         np.testing.assert_allclose(P[k], p, rtol=0.0, atol=1e-13, err_msg="step %d" % k)
     sim.close()
+
+
+@pytest.mark.parametrize("preset,precision", [("small2d", "fp32"), ("small3d", "fp32"), ("small3d", "fp64")])
+def test_record_leaves_the_step_unchanged(preset, precision):
+    """The push that keeps the record is a kernel of its own (held to 256
+    registers; in FP64 3D it spills a few): with the record on, particles
+    and fields after the steps equal those of the push without it, to the
+    rounding of the shared-memory current sums (their order varies)."""
+    from parity_util import field_error, max_particle_error, thermal_floor
+    _say("record leaves the step unchanged", preset, precision)
+    spec = synth.preset(preset)
+    state = synth.make_state(spec)
+    cfg = S.config_from_spec(spec, precision=precision)
+    a = S.Simulation(cfg, state["particles"], state["fields"])
+    b = S.Simulation(cfg, state["particles"], state["fields"])
+    b.record_polarization(-1, capacity=16)
+    a.step(12)
+    b.step(12)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k in range(len(spec["species"])):
+        e = max_particle_error(b.particles(k), a.particles(k), spec, thermal_floor(spec, k))
+        assert e <= tol, (k, e)
+    Fa, Fb = a.fields(), b.fields()
+    for nm in S.FIELD_NAMES[:9]:
+        assert field_error(Fb[nm], Fa[nm]) <= tol, nm
+    P, N = b.polarization_history()
+    assert N.size == 12
+    a.close()
+    b.close()
