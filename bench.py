@@ -690,9 +690,8 @@ def run_schedule(S, spec, state, precision, acc, warmup, steps, tile=None, windo
     del sim
     torch.cuda.synchronize()
     # hand the freed stores back to the device, so that the next run of this
-    # process starts as a run in a fresh process would (the c3 FP64 push over
-    # its later steps took 19.6 ms after four runs' cached blocks, 11.2 ms in
-    # a process of its own)
+    # process starts as a run in a fresh process would, with nothing that an
+    # earlier run left in torch's cache
     torch.cuda.empty_cache()
     return out
 
